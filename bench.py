@@ -1,0 +1,297 @@
+#!/usr/bin/env python3
+"""Throughput of the fused piecewise sin+cos+tan map (arXiv 2502.10831) on one
+MI355X.
+
+One step = one ta_sincos call (sin, cos and tan outputs) over 2^28 FP32
+inputs already resident in HBM: 99% U[-1000, 1000] and 1% within 1e-3 of odd
+multiples of pi/2.  Prints ONE JSON line with Gelem/s, the HBM roofline of the
+kernel (HIP events on the launch stream), the FP64 CPU oracle timed on the
+host, the GPU's built-in sinf/cosf/tanf and __sinf/__cosf/__tanf in the same
+skeleton (each with its max error against FP64 libm), the Taylor-5 baseline,
+the copy ceiling, and the fused forward+backward activation workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, AMD published
+METRIC = ("Gelem/s + % HBM peak, ta_sincos FP32 2^28 vs HIP sinf/cosf at "
+          "stated max err")
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "ta_sincos_tan_f32_2p28_pmc.txt")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2502_10831_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def time_launches(fn, steps, warmup, torch):
+    """Per-launch durations (ms) with HIP events on torch's current stream,
+    which is the stream every ta_* call launches on."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True),
+           torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3
+    per = [a.elapsed_time(b) for a, b in ev]
+    total = ev[0][0].elapsed_time(ev[-1][1])
+    return per, total, wall
+
+
+def pmc_traffic():
+    """HBM bytes per launch from the committed rocprofv3 --pmc summary, or
+    None when it is missing or was taken on other kernel sources."""
+    if not os.path.exists(PMC_SUMMARY):
+        return None
+    vals = {}
+    with open(PMC_SUMMARY) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("source_sha") != source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the headline kernel (for profiling runs)")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: the map has no cross-GPU step and "
+              "this build runs on a single MI355X (use --gpus 1).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2502_10831_amd as ta
+    from paper_2502_10831_amd import workloads as wl
+
+    dev = torch.device("cuda:0")
+    ta.load()
+    n = 1 << 28
+    log("generating 2^28 FP32 inputs")
+    x_host = wl.throughput_mix(n)
+    x = torch.from_numpy(x_host).to(dev)
+    ys, yc, yt = (torch.empty_like(x) for _ in range(3))
+
+    def step():
+        ta.ta_sincos(x, ys, yc, yt)
+
+    log("timing ta_sincos (sin+cos+tan)")
+    per, total, wall = time_launches(step, args.steps, args.warmup, torch)
+    ms_per_step = total / args.steps
+    kernel_ms = sum(per) / len(per)
+    gelem = n / (ms_per_step * 1e-3) / 1e9
+    alg_bytes = 16 * n
+    achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
+    traffic = pmc_traffic()
+    out = {
+        "metric": METRIC,
+        "value": round(gelem, 2),
+        "unit": "Gelem/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "ta_sincos sin+cos+tan, 2^28 FP32, 99% U[-1000,1000] "
+                        "+ 1% within 1e-3 of odd multiples of pi/2 "
+                        "(seed 2024873)",
+            "n": n, "outputs": 3, "bytes_per_elem": 16,
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "kernel": "map_vec_kernel<F32, FwdOp<sin|cos|tan>>",
+            "kernel_ms": round(kernel_ms, 5),
+            "algorithmic_bytes_per_launch": alg_bytes,
+        },
+    }
+    host_wall_ms = wall / args.steps
+    out["timing_note"] = {"host_wall_ms_per_step": round(host_wall_ms, 4)}
+
+    if not args.no_extras:
+        out["cpu_baseline"] = cpu_baseline(x_host, args.cpu_seconds)
+        out["comparators"] = comparators(x, x_host, n, args, torch, ta, np)
+        out["extra"] = extras(args, torch, ta, dev)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(x_host, seconds):
+    """The FP64 oracle (untuned) on the host cores, bounded sample of the
+    same workload, sin+cos+tan outputs."""
+    import numpy as np
+
+    import oracle
+
+    threads = min(os.cpu_count() or 1, 16)
+    probe = x_host[: 1 << 18].astype(np.float64)
+    t0 = time.perf_counter()
+    oracle.forward(probe, nthreads=threads)
+    dt = time.perf_counter() - t0
+    m = int(min(len(x_host), max(1 << 18, probe.size * seconds / max(dt, 1e-6))))
+    sample = x_host[:m].astype(np.float64)
+    log(f"cpu baseline: oracle on {m} elements, {threads} threads")
+    t0 = time.perf_counter()
+    r = oracle.forward(sample, nthreads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": round(m / dt / 1e9, 5), "unit": "Gelem/s",
+            "cores": int(r["threads"]), "kind": "oracle",
+            "sample": f"first {m} elements of the 2^28 workload, "
+                      f"sin+cos+tan, {dt:.1f} s"}
+
+
+def comparators(x, x_host, n, args, torch, ta, np):
+    """Built-in functions and Taylor-5 in the same skeleton, each with its
+    max error against FP64 libm on a 2^20-element sample."""
+    res = {}
+    idx = np.random.default_rng(3).choice(n, 1 << 20, replace=False)
+    xs = x_host[idx].astype(np.float64)
+    it = torch.from_numpy(idx).to(x.device)
+    ref = {"sin": np.sin(xs), "cos": np.cos(xs), "tan": np.tan(xs)}
+    poleok = np.abs(np.cos(xs)) > 1e-3
+
+    def errors(outs):
+        e = {}
+        for name, t in outs.items():
+            g = t[it].double().cpu().numpy()
+            if name == "tan":
+                rel = np.abs(g - ref[name]) / np.abs(ref[name])
+                e["tan_max_rel"] = float(rel[poleok].max())
+            else:
+                e[f"{name}_max_abs"] = float(np.abs(g - ref[name]).max())
+        return e
+
+    ys, yc, yt = (torch.empty_like(x) for _ in range(3))
+    ta.ta_sincos(x, ys, yc, yt)
+    res["ta_sincos_tan"] = {"error_vs_libm": errors({"sin": ys, "cos": yc,
+                                                      "tan": yt})}
+    for kind, label in ((0, "builtin_sinf_cosf_tanf"),
+                        (1, "builtin___sinf___cosf___tanf")):
+        def f(kind=kind):
+            ta.ta_builtin_sincos(x, ys, yc, yt, kind=kind)
+        log(f"timing {label}")
+        per, total, _ = time_launches(f, args.steps, args.warmup, torch)
+        ms = total / args.steps
+        res[label] = {"gelem_s": round(n / (ms * 1e-3) / 1e9, 2),
+                      "ms": round(ms, 5),
+                      "error_vs_libm": errors({"sin": ys, "cos": yc,
+                                               "tan": yt})}
+
+    def f2():
+        ta.ta_sincos(x, ys, yc, None)
+    per, total, _ = time_launches(f2, args.steps, args.warmup, torch)
+    ms = total / args.steps
+    res["ta_sincos_2out"] = {"gelem_s": round(n / (ms * 1e-3) / 1e9, 2),
+                             "gbs": round(12 * n / (ms * 1e-3) / 1e9, 1)}
+
+    def f3():
+        ta.ta_taylor_sin(x, ys, 5)
+    per, total, _ = time_launches(f3, args.steps, args.warmup, torch)
+    ms = total / args.steps
+    res["ta_taylor_sin_5"] = {"gelem_s": round(n / (ms * 1e-3) / 1e9, 2),
+                              "gbs": round(8 * n / (ms * 1e-3) / 1e9, 1)}
+
+    def f4():
+        ta.ta_sin(x, ys)
+    per, total, _ = time_launches(f4, args.steps, args.warmup, torch)
+    ms = total / args.steps
+    res["ta_sin"] = {"gelem_s": round(n / (ms * 1e-3) / 1e9, 2),
+                     "gbs": round(8 * n / (ms * 1e-3) / 1e9, 1)}
+
+    def fc():
+        ta.ta_copy([x], [ys, yc, yt])
+    per, total, _ = time_launches(fc, args.steps, args.warmup, torch)
+    ms = total / args.steps
+    res["copy_1in_3out_ceiling"] = {"gbs": round(16 * n / (ms * 1e-3) / 1e9, 1),
+                                    "ms": round(ms, 5)}
+    return res
+
+
+def extras(args, torch, ta, dev):
+    """Fused forward+backward activation, [128, 8192, 512] FP32,
+    x ~ N(0, 10^2), g ~ N(0, 1)."""
+    res = {}
+    n = 128 * 8192 * 512
+    gen = torch.Generator(device=dev).manual_seed(2024873)
+    x = torch.randn(n, device=dev, generator=gen) * 10.0
+    g = torch.randn(n, device=dev, generator=gen)
+    y, gx = torch.empty_like(x), torch.empty_like(x)
+
+    def fused():
+        ta.ta_sin_fwdbwd(x, g, y, gx)
+
+    def separate():
+        ta.ta_sin(x, y)
+        ta.ta_sin_bwd(x, g, gx)
+
+    def torch_ref():
+        torch.sin(x, out=y)
+        torch.mul(g, torch.cos(x), out=gx)
+
+    def copy22():
+        ta.ta_copy([x, g], [y, gx])
+
+    for label, fn, nbytes in (("fused_fwdbwd", fused, 16),
+                              ("separate_fwd_then_bwd", separate, 20),
+                              ("torch_sin_then_g_times_cos", torch_ref, 28),
+                              ("copy_2in_2out_ceiling", copy22, 16)):
+        log(f"timing {label}")
+        per, total, _ = time_launches(fn, max(5, args.steps // 2), 3, torch)
+        ms = total / max(5, args.steps // 2)
+        res[label] = {"ms": round(ms, 5),
+                      "gelem_s": round(n / (ms * 1e-3) / 1e9, 2),
+                      "gbs_algorithmic": round(nbytes * n / (ms * 1e-3) / 1e9, 1)}
+    res["fused_fwdbwd"]["hbm_frac"] = round(
+        res["fused_fwdbwd"]["gbs_algorithmic"] / HBM_PEAK_GBS, 4)
+    res["workload"] = ("ta_sin_fwdbwd, [128, 8192, 512] FP32, x ~ N(0, 100), "
+                       "g ~ N(0, 1)")
+    return res
+
+
+if __name__ == "__main__":
+    main()

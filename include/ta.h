@@ -1,0 +1,152 @@
+/*
+ * ta.h -- C ABI of libta.so: elementwise piecewise trigonometric
+ * approximations (Goyal & Arora, arXiv 2502.10831) on AMD Instinct MI355X
+ * (gfx950) device arrays.
+ *
+ * The method (Section 2 of the paper, derived in Appendix A): an angle is
+ * folded to rho in [0, pi/2] with a sign (Section 3); rho selects one of six
+ * pieces of width pi/12; on piece k, with t = rho in degrees,
+ *     N = a_k t + b_k,   D = c_k t + d_k       (Appendix A, eqs. 5-10)
+ *     tan = N / D,   sin = N / sqrt(N^2 + D^2),   cos = D / sqrt(N^2 + D^2)
+ * (Appendix A.4).  Arithmetic: argument reduction and the two linear forms
+ * in FP64, everything after (the quadratic, inverse square root, quotient)
+ * in FP32.  Results agree with a plain FP64 evaluation of the same formulas
+ * to within 4 FP32 ulp.
+ *
+ * Conventions for every entry point:
+ *  - Buffers are device pointers owned by the caller, contiguous, all of the
+ *    same storage dtype `dt`.  The library never allocates, frees or
+ *    synchronises.  Work is enqueued on `stream` (NULL = default stream);
+ *    results are valid once the caller synchronises that stream.
+ *  - `n` is the element count.  n == 0 returns TA_OK without a launch.
+ *  - Errors detected before any HIP call (so also testable without a GPU):
+ *      TA_EINVAL   n < 0, a required pointer NULL while n > 0, a bad `terms`
+ *                  or unknown flag bits;
+ *      TA_EDTYPE   `dt` is not one of ta_dtype;
+ *      TA_EOVERLAP an output partially overlaps an input or another output
+ *                  (an output may alias an input exactly: in-place).
+ *    TA_EHIP: the kernel launch failed; ta_last_hip_error() returns the
+ *    hipError_t of the calling thread's last failure.
+ *  - Any alignment is accepted.  When every buffer has the same address
+ *    modulo 16 the body runs with 16-byte vector accesses (a scalar head and
+ *    tail are peeled); otherwise a scalar path runs.
+ *  - Calls are reentrant and thread-safe: there is no mutable global state.
+ *  - Inputs: any value.  NaN and +-Inf give NaN; sin and tan keep the sign of
+ *    a zero input; cos(+-0) = 1.  Every finite input is reduced exactly
+ *    enough for the 4-ulp agreement (FP64 Cody-Waite below 2^29 in magnitude,
+ *    a 2/pi bit-table reduction above).
+ */
+#ifndef TA_H_
+#define TA_H_
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { TA_F32 = 0, TA_F16 = 1, TA_BF16 = 2 } ta_dtype;
+
+typedef enum {
+  TA_OK = 0,
+  TA_EINVAL = 1,
+  TA_EDTYPE = 2,
+  TA_EOVERLAP = 3,
+  TA_EHIP = 4
+} ta_status;
+
+/* Flag bits for the *_ex forward calls. */
+enum {
+  /* The pseudocode of proposed_tan (Section 3) returns +infinity, before the
+   * sign is applied, when the folded angle is within 1e-3 of pi/2.  Off by
+   * default (the formula is then used all the way to the pole). */
+  TA_FLAG_TAN_GUARD = 1u
+};
+
+/* ---- forward: the proposed functions (Section 2 formulas, Section 3 fold) */
+
+/* y[i] = sin_a(x[i]).  Section 2 "Sine Function" cases. */
+ta_status ta_sin(const void *x, void *y, int64_t n, ta_dtype dt,
+                 hipStream_t stream);
+/* y[i] = cos_a(x[i]).  Section 2 "Cosine Function" cases. */
+ta_status ta_cos(const void *x, void *y, int64_t n, ta_dtype dt,
+                 hipStream_t stream);
+/* y[i] = tan_a(x[i]).  Section 2 "Tangent Function" cases; finite up to the
+ * pole (the last piece's D vanishes only at exactly pi/2). */
+ta_status ta_tan(const void *x, void *y, int64_t n, ta_dtype dt,
+                 hipStream_t stream);
+/* Fused: one reduction per element, ys = sin_a, yc = cos_a and, when `yt` is
+ * not NULL, yt = tan_a.  `ys` and `yc` are required. */
+ta_status ta_sincos(const void *x, void *ys, void *yc, void *yt, int64_t n,
+                    ta_dtype dt, hipStream_t stream);
+/* Same as above with flag bits (TA_FLAG_TAN_GUARD affects tan outputs). */
+ta_status ta_tan_ex(const void *x, void *y, int64_t n, ta_dtype dt,
+                    uint32_t flags, hipStream_t stream);
+ta_status ta_sincos_ex(const void *x, void *ys, void *yc, void *yt, int64_t n,
+                       ta_dtype dt, uint32_t flags, hipStream_t stream);
+
+/* ---- Taylor baseline (Section 3 "Taylor series"; Tables 1-3 columns) ----
+ * The first `terms` (5, 7 or 9) non-zero Maclaurin terms of sin, cos or tan,
+ * in FP32 Horner form, evaluated on the same folded angle rho in [0, pi/2]
+ * with the same signs.  terms outside {5, 7, 9} -> TA_EINVAL. */
+ta_status ta_taylor_sin(const void *x, void *y, int64_t n, int terms,
+                        ta_dtype dt, hipStream_t stream);
+ta_status ta_taylor_cos(const void *x, void *y, int64_t n, int terms,
+                        ta_dtype dt, hipStream_t stream);
+ta_status ta_taylor_tan(const void *x, void *y, int64_t n, int terms,
+                        ta_dtype dt, hipStream_t stream);
+
+/* ---- backward: analytic derivative of the selected piece ----------------
+ * Differentiating Appendix A.4 on piece k gives, with
+ * omega = (180/pi) (a_k d_k - b_k c_k) / (N^2 + D^2):
+ *   d sin_a/dx = omega cos_a(x),  d cos_a/dx = -omega sin_a(x),
+ *   d tan_a/dx = omega (1 + tan_a(x)^2)        in every quadrant.
+ * The approximation jumps at 15, 30, 60 and 75 degrees and has a kink at 45;
+ * there the derivative of the piece selected by the forward is returned.
+ * gx[i] = gy[i] * d f/dx (x[i]).  x, gy, gx share the dtype. */
+ta_status ta_sin_bwd(const void *x, const void *gy, void *gx, int64_t n,
+                     ta_dtype dt, hipStream_t stream);
+ta_status ta_cos_bwd(const void *x, const void *gy, void *gx, int64_t n,
+                     ta_dtype dt, hipStream_t stream);
+ta_status ta_tan_bwd(const void *x, const void *gy, void *gx, int64_t n,
+                     ta_dtype dt, hipStream_t stream);
+/* gx = gs * d sin_a/dx + gc * d cos_a/dx.  Either gs or gc may be NULL
+ * (treated as zero); not both. */
+ta_status ta_sincos_bwd(const void *x, const void *gs, const void *gc,
+                        void *gx, int64_t n, ta_dtype dt, hipStream_t stream);
+
+/* ---- fused forward + backward in one pass (reads x, gy; writes y, gx) --- */
+ta_status ta_sin_fwdbwd(const void *x, const void *gy, void *y, void *gx,
+                        int64_t n, ta_dtype dt, hipStream_t stream);
+ta_status ta_cos_fwdbwd(const void *x, const void *gy, void *y, void *gx,
+                        int64_t n, ta_dtype dt, hipStream_t stream);
+ta_status ta_tan_fwdbwd(const void *x, const void *gy, void *y, void *gx,
+                        int64_t n, ta_dtype dt, hipStream_t stream);
+
+/* ---- measurement comparators (not part of the method) -------------------
+ * The same load/store skeleton around the GPU's built-in functions:
+ *   kind 0: sinf / cosf / tanf (accurate device library)
+ *   kind 1: __sinf / __cosf / __tanf (hardware approximations)
+ *   kind 2: sincosf + tanf
+ * ys, yc required; yt may be NULL.  F32 only (TA_EDTYPE otherwise). */
+ta_status ta_builtin_sincos(const void *x, void *ys, void *yc, void *yt,
+                            int64_t n, int kind, ta_dtype dt,
+                            hipStream_t stream);
+/* Plain streaming copy with the same access pattern as the kernels: reads
+ * n_in input arrays (1..3) and writes n_out outputs (1..3), out[j][i] =
+ * in[j % n_in][i].  The achievable HBM ceiling for that byte mix. */
+ta_status ta_copy(const void *const *in, int n_in, void *const *out,
+                  int n_out, int64_t n, ta_dtype dt, hipStream_t stream);
+
+/* ---- utilities ---------------------------------------------------------- */
+const char *ta_status_str(ta_status s);
+/* hipError_t of the calling thread's last TA_EHIP (0 if none). */
+int ta_last_hip_error(void);
+const char *ta_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TA_H_ */

@@ -1,0 +1,583 @@
+// ta_kernels.hip -- gfx950 kernels and the C ABI of libta.so.
+//
+// Every entry point is an elementwise map: NIN input streams, NOUT output
+// streams, one functor per element.  The streaming skeleton issues 16-byte
+// global loads and stores (4 FP32 or 8 16-bit elements per access), UNROLL
+// accesses per stream per thread with all loads issued before any compute,
+// 256-thread workgroups, and 64-bit indexing.  The per-piece coefficients
+// live in LDS (one 200-byte copy per workgroup), never in HBM.
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+#include <string.h>
+
+#include "ta.h"
+#include "ta_math.hpp"
+
+namespace ta {
+
+constexpr int kBlock = 256;
+
+// ---------------------------------------------------------------------------
+// Storage formats.  Loads widen exactly to FP32; stores round to nearest
+// even.
+// ---------------------------------------------------------------------------
+struct F32 {
+  using raw = uint32_t;
+  static __device__ float load(raw v) { return __uint_as_float(v); }
+  static __device__ raw store(float f) { return __float_as_uint(f); }
+};
+struct F16 {
+  using raw = uint16_t;
+  static __device__ float load(raw v) {
+    return __half2float(__ushort_as_half(v));
+  }
+  static __device__ raw store(float f) {
+    return __half_as_ushort(__float2half_rn(f));
+  }
+};
+struct BF16 {
+  using raw = uint16_t;
+  static __device__ float load(raw v) { return __uint_as_float(uint32_t(v) << 16); }
+  static __device__ raw store(float f) {
+    const uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return raw((u >> 16) | 0x40u);  // NaN
+    return raw((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Element functors.  in[]/out[] are FP32 values; `tb` is the LDS table.
+// ---------------------------------------------------------------------------
+enum : int { kSin = 1, kCos = 2, kTan = 4 };
+
+template <int MASK, bool GUARD>
+struct FwdOp {
+  static constexpr int NIN = 1;
+  static constexpr int NOUT = ((MASK & kSin) ? 1 : 0) + ((MASK & kCos) ? 1 : 0) +
+                              ((MASK & kTan) ? 1 : 0);
+  static constexpr bool kNeedsTables = true;
+  __device__ static void apply(const float *in, float *out, const Tables &tb) {
+    const Folded f = fold(in[0]);
+    const Forms v = forms(f, tb);
+    int o = 0;
+    if constexpr ((MASK & (kSin | kCos)) != 0) {
+      const float y = rsqrt_refined(v.q);
+      if constexpr (MASK & kSin) out[o++] = with_sign(v.n * y, sin_sign(f));
+      if constexpr (MASK & kCos) out[o++] = with_sign(v.d * y, cos_sign(f));
+    }
+    if constexpr (MASK & kTan) {
+      float t = with_sign(div_refined(v.n, v.d), tan_sign(f));
+      if constexpr (GUARD) {
+        // Section 3 proposed_tan: +inf within 1e-3 of pi/2, before the sign.
+        if ((f.q & 1u) && f.a < 1e-3) t = __builtin_inff();
+      }
+      out[o++] = t;
+    }
+  }
+};
+
+template <int MASK, int TERMS>
+struct TaylorOp {
+  static constexpr int NIN = 1;
+  static constexpr int NOUT = 1;
+  static constexpr bool kNeedsTables = false;
+  __device__ static void apply(const float *in, float *out, const Tables &) {
+    const Folded f = fold(in[0]);
+    const float rho = fold_rho(f);
+    if constexpr (MASK == kSin)
+      out[0] = with_sign(taylor_sin_unsigned<TERMS>(rho), sin_sign(f));
+    if constexpr (MASK == kCos)
+      out[0] = with_sign(taylor_cos_unsigned<TERMS>(rho), cos_sign(f));
+    if constexpr (MASK == kTan)
+      out[0] = with_sign(taylor_tan_unsigned<TERMS>(rho), tan_sign(f));
+  }
+};
+
+// d/dx of the selected piece times the upstream gradient(s).
+//   sin: gx = gy * omega * cos_a     cos: gx = -gy * omega * sin_a
+//   tan: gx = gy * (180/pi) det / D^2
+// WITH_Y also writes the forward value (the fused forward+backward).
+template <int WHICH, bool WITH_Y>
+struct BwdOp {
+  static constexpr int NIN = 2;  // x, gy
+  static constexpr int NOUT = WITH_Y ? 2 : 1;
+  static constexpr bool kNeedsTables = true;
+  __device__ static void apply(const float *in, float *out, const Tables &tb) {
+    const Folded f = fold(in[0]);
+    const Forms v = forms(f, tb);
+    const float kdet = tb.kdet[f.idx];
+    if constexpr (WHICH == kTan) {
+      const float r = rcp_refined(v.d);
+      const float dt = kdet * r * r;
+      if constexpr (WITH_Y) out[0] = with_sign(div_refined(v.n, v.d), tan_sign(f));
+      out[WITH_Y ? 1 : 0] = in[1] * dt;
+    } else {
+      const float y = rsqrt_refined(v.q);
+      const float s = with_sign(v.n * y, sin_sign(f));
+      const float c = with_sign(v.d * y, cos_sign(f));
+      const float omega = kdet * y * y;
+      if constexpr (WHICH == kSin) {
+        if constexpr (WITH_Y) out[0] = s;
+        out[WITH_Y ? 1 : 0] = in[1] * (omega * c);
+      } else {
+        if constexpr (WITH_Y) out[0] = c;
+        out[WITH_Y ? 1 : 0] = -(in[1] * (omega * s));
+      }
+    }
+  }
+};
+
+// gx = gs * d sin_a/dx + gc * d cos_a/dx = omega (gs cos_a - gc sin_a).
+template <bool HAS_GS, bool HAS_GC>
+struct SinCosBwdOp {
+  static constexpr int NIN = 1 + (HAS_GS ? 1 : 0) + (HAS_GC ? 1 : 0);
+  static constexpr int NOUT = 1;
+  static constexpr bool kNeedsTables = true;
+  __device__ static void apply(const float *in, float *out, const Tables &tb) {
+    const Folded f = fold(in[0]);
+    const Forms v = forms(f, tb);
+    const float y = rsqrt_refined(v.q);
+    const float omega = tb.kdet[f.idx] * y * y;
+    float acc = 0.0f;
+    if constexpr (HAS_GS) acc = in[1] * with_sign(v.d * y, cos_sign(f));
+    if constexpr (HAS_GC)
+      acc = __builtin_fmaf(-in[HAS_GS ? 2 : 1], with_sign(v.n * y, sin_sign(f)),
+                           acc);
+    out[0] = omega * acc;
+  }
+};
+
+// Comparators: the GPU's built-in functions in the same skeleton.
+template <int KIND, bool WITH_TAN>
+struct BuiltinOp {
+  static constexpr int NIN = 1;
+  static constexpr int NOUT = WITH_TAN ? 3 : 2;
+  static constexpr bool kNeedsTables = false;
+  __device__ static void apply(const float *in, float *out, const Tables &) {
+    const float x = in[0];
+    if constexpr (KIND == 0) {
+      out[0] = sinf(x);
+      out[1] = cosf(x);
+      if constexpr (WITH_TAN) out[2] = tanf(x);
+    } else if constexpr (KIND == 1) {
+      out[0] = __sinf(x);
+      out[1] = __cosf(x);
+      if constexpr (WITH_TAN) out[2] = __tanf(x);
+    } else {
+      float s, c;
+      sincosf(x, &s, &c);
+      out[0] = s;
+      out[1] = c;
+      if constexpr (WITH_TAN) out[2] = tanf(x);
+    }
+  }
+};
+
+template <int NI, int NO>
+struct CopyOp {
+  static constexpr int NIN = NI;
+  static constexpr int NOUT = NO;
+  static constexpr bool kNeedsTables = false;
+  __device__ static void apply(const float *in, float *out, const Tables &) {
+#pragma unroll
+    for (int j = 0; j < NO; ++j) out[j] = in[j % NI];
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Streaming skeleton
+// ---------------------------------------------------------------------------
+struct IoPtrs {
+  const char *in[3];
+  char *out[3];
+};
+
+template <class ST>
+struct Vec {
+  static constexpr int kElems = 16 / int(sizeof(typename ST::raw));
+};
+
+template <class ST, class Op>
+__device__ inline void scalar_element(const IoPtrs &io, int64_t i,
+                                      const Tables &tb) {
+  using raw = typename ST::raw;
+  float in[Op::NIN], out[Op::NOUT];
+#pragma unroll
+  for (int k = 0; k < Op::NIN; ++k)
+    in[k] = ST::load(reinterpret_cast<const raw *>(io.in[k])[i]);
+  Op::apply(in, out, tb);
+#pragma unroll
+  for (int k = 0; k < Op::NOUT; ++k)
+    reinterpret_cast<raw *>(io.out[k])[i] = ST::store(out[k]);
+}
+
+// Vector body: elements [head, head + nvec*VEC) in 16-byte accesses; block 0
+// also does the scalar head [0, head) and tail [head + nvec*VEC, n).
+template <class ST, class Op, int UNROLL>
+__global__ __launch_bounds__(kBlock) void map_vec_kernel(IoPtrs io, int64_t head,
+                                                         int64_t nvec, int64_t n) {
+  using raw = typename ST::raw;
+  constexpr int VEC = Vec<ST>::kElems;
+  __shared__ Tables tb;
+  if constexpr (Op::kNeedsTables) {
+    init_tables(tb);
+    __syncthreads();
+  }
+  const int64_t v0 = int64_t(blockIdx.x) * (UNROLL * kBlock) + threadIdx.x;
+  uint4 in_raw[UNROLL][Op::NIN];
+#pragma unroll
+  for (int u = 0; u < UNROLL; ++u) {
+    const int64_t v = v0 + int64_t(u) * kBlock;
+    if (v < nvec) {
+#pragma unroll
+      for (int k = 0; k < Op::NIN; ++k)
+        in_raw[u][k] = reinterpret_cast<const uint4 *>(
+            io.in[k] + head * int64_t(sizeof(raw)))[v];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < UNROLL; ++u) {
+    const int64_t v = v0 + int64_t(u) * kBlock;
+    if (v < nvec) {
+      uint4 out_raw[Op::NOUT];
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) {
+        float in[Op::NIN], out[Op::NOUT];
+#pragma unroll
+        for (int k = 0; k < Op::NIN; ++k)
+          in[k] = ST::load(reinterpret_cast<const raw *>(&in_raw[u][k])[e]);
+        Op::apply(in, out, tb);
+#pragma unroll
+        for (int k = 0; k < Op::NOUT; ++k)
+          reinterpret_cast<raw *>(&out_raw[k])[e] = ST::store(out[k]);
+      }
+#pragma unroll
+      for (int k = 0; k < Op::NOUT; ++k)
+        reinterpret_cast<uint4 *>(io.out[k] + head * int64_t(sizeof(raw)))[v] =
+            out_raw[k];
+    }
+  }
+  if (blockIdx.x == 0) {
+    const int64_t tail0 = head + nvec * VEC;
+    const int64_t extra = head + (n - tail0);
+    for (int64_t e = threadIdx.x; e < extra; e += kBlock)
+      scalar_element<ST, Op>(io, e < head ? e : tail0 + (e - head), tb);
+  }
+}
+
+// Fallback when the buffers disagree on their address modulo 16.
+template <class ST, class Op>
+__global__ __launch_bounds__(kBlock) void map_scalar_kernel(IoPtrs io, int64_t n) {
+  __shared__ Tables tb;
+  if constexpr (Op::kNeedsTables) {
+    init_tables(tb);
+    __syncthreads();
+  }
+  const int64_t stride = int64_t(gridDim.x) * kBlock;
+  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride)
+    scalar_element<ST, Op>(io, i, tb);
+}
+
+template <class Op>
+struct Unroll {
+  static constexpr int value = 2;
+};
+
+template <class ST, class Op>
+hipError_t launch_map(const void *const *in, void *const *out, int64_t n,
+                      hipStream_t stream) {
+  using raw = typename ST::raw;
+  constexpr int VEC = Vec<ST>::kElems;
+  constexpr int UNROLL = Unroll<Op>::value;
+  IoPtrs io{};
+  const uintptr_t mis = uintptr_t(in[0]) & 15u;
+  bool same = (mis % sizeof(raw)) == 0;
+  for (int k = 0; k < Op::NIN; ++k) {
+    io.in[k] = static_cast<const char *>(in[k]);
+    same = same && ((uintptr_t(in[k]) & 15u) == mis);
+  }
+  for (int k = 0; k < Op::NOUT; ++k) {
+    io.out[k] = static_cast<char *>(out[k]);
+    same = same && ((uintptr_t(out[k]) & 15u) == mis);
+  }
+  if (same) {
+    int64_t head = mis ? int64_t((16u - mis) / sizeof(raw)) : 0;
+    if (head > n) head = n;
+    const int64_t nvec = (n - head) / VEC;
+    const int64_t per_block = int64_t(UNROLL) * kBlock;
+    int64_t blocks = (nvec + per_block - 1) / per_block;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL((map_vec_kernel<ST, Op, UNROLL>), dim3(unsigned(blocks)),
+                       dim3(kBlock), 0, stream, io, head, nvec, n);
+  } else {
+    int64_t blocks = (n + kBlock - 1) / kBlock;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL((map_scalar_kernel<ST, Op>), dim3(unsigned(blocks)),
+                       dim3(kBlock), 0, stream, io, n);
+  }
+  return hipGetLastError();
+}
+
+template <class Op>
+hipError_t launch_dtype(ta_dtype dt, const void *const *in, void *const *out,
+                        int64_t n, hipStream_t s) {
+  switch (dt) {
+    case TA_F32: return launch_map<F32, Op>(in, out, n, s);
+    case TA_F16: return launch_map<F16, Op>(in, out, n, s);
+    case TA_BF16: return launch_map<BF16, Op>(in, out, n, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// Host-side validation (before any HIP call)
+// ---------------------------------------------------------------------------
+thread_local int g_last_hip_error = 0;
+
+inline size_t dtype_size(ta_dtype dt) { return dt == TA_F32 ? 4 : 2; }
+inline bool dtype_ok(int dt) { return dt == TA_F32 || dt == TA_F16 || dt == TA_BF16; }
+
+// Outputs may alias an input exactly; any other overlap is an error.
+inline bool overlap_ok(const void *const *in, int nin, void *const *out,
+                       int nout, int64_t n, size_t es) {
+  const uintptr_t bytes = uintptr_t(n) * es;
+  auto inter = [&](uintptr_t a, uintptr_t b) { return a < b + bytes && b < a + bytes; };
+  for (int j = 0; j < nout; ++j) {
+    const uintptr_t o = uintptr_t(out[j]);
+    for (int i = 0; i < nin; ++i) {
+      const uintptr_t p = uintptr_t(in[i]);
+      if (o != p && inter(o, p)) return false;
+    }
+    for (int k = 0; k < j; ++k)
+      if (inter(o, uintptr_t(out[k]))) return false;
+  }
+  return true;
+}
+
+inline ta_status check_common(const void *const *in, int nin, void *const *out,
+                              int nout, int64_t n, int dt) {
+  if (!dtype_ok(dt)) return TA_EDTYPE;
+  if (n < 0) return TA_EINVAL;
+  if (n == 0) return TA_OK;
+  for (int i = 0; i < nin; ++i)
+    if (!in[i]) return TA_EINVAL;
+  for (int j = 0; j < nout; ++j)
+    if (!out[j]) return TA_EINVAL;
+  if (!overlap_ok(in, nin, out, nout, n, dtype_size(ta_dtype(dt))))
+    return TA_EOVERLAP;
+  return TA_OK;
+}
+
+inline ta_status finish(hipError_t e) {
+  if (e != hipSuccess) {
+    g_last_hip_error = int(e);
+    return TA_EHIP;
+  }
+  return TA_OK;
+}
+
+template <class Op>
+ta_status run(const void *const *in, void *const *out, int64_t n, ta_dtype dt,
+              hipStream_t s) {
+  const ta_status st = check_common(in, Op::NIN, out, Op::NOUT, n, dt);
+  if (st != TA_OK || n == 0) return st;
+  return finish(launch_dtype<Op>(dt, in, out, n, s));
+}
+
+template <int MASK, bool GUARD>
+ta_status fwd(const void *x, void *const *outs, int64_t n, ta_dtype dt,
+              hipStream_t s) {
+  const void *in[1] = {x};
+  return run<FwdOp<MASK, GUARD>>(in, outs, n, dt, s);
+}
+
+template <int MASK>
+ta_status taylor(const void *x, void *y, int64_t n, int terms, ta_dtype dt,
+                 hipStream_t s) {
+  if (!dtype_ok(dt)) return TA_EDTYPE;
+  const void *in[1] = {x};
+  void *out[1] = {y};
+  switch (terms) {
+    case 5: return run<TaylorOp<MASK, 5>>(in, out, n, dt, s);
+    case 7: return run<TaylorOp<MASK, 7>>(in, out, n, dt, s);
+    case 9: return run<TaylorOp<MASK, 9>>(in, out, n, dt, s);
+  }
+  return TA_EINVAL;
+}
+
+template <int WHICH, bool WITH_Y>
+ta_status bwd(const void *x, const void *gy, void *y, void *gx, int64_t n,
+              ta_dtype dt, hipStream_t s) {
+  const void *in[2] = {x, gy};
+  if constexpr (WITH_Y) {
+    void *out[2] = {y, gx};
+    return run<BwdOp<WHICH, true>>(in, out, n, dt, s);
+  } else {
+    void *out[1] = {gx};
+    return run<BwdOp<WHICH, false>>(in, out, n, dt, s);
+  }
+}
+
+}  // namespace ta
+
+using namespace ta;
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+ta_status ta_sin(const void *x, void *y, int64_t n, ta_dtype dt, hipStream_t s) {
+  void *o[1] = {y};
+  return fwd<kSin, false>(x, o, n, dt, s);
+}
+
+ta_status ta_cos(const void *x, void *y, int64_t n, ta_dtype dt, hipStream_t s) {
+  void *o[1] = {y};
+  return fwd<kCos, false>(x, o, n, dt, s);
+}
+
+ta_status ta_tan_ex(const void *x, void *y, int64_t n, ta_dtype dt,
+                    uint32_t flags, hipStream_t s) {
+  if (flags & ~uint32_t(TA_FLAG_TAN_GUARD)) return TA_EINVAL;
+  void *o[1] = {y};
+  if (flags & TA_FLAG_TAN_GUARD) return fwd<kTan, true>(x, o, n, dt, s);
+  return fwd<kTan, false>(x, o, n, dt, s);
+}
+
+ta_status ta_tan(const void *x, void *y, int64_t n, ta_dtype dt, hipStream_t s) {
+  return ta_tan_ex(x, y, n, dt, 0u, s);
+}
+
+ta_status ta_sincos_ex(const void *x, void *ys, void *yc, void *yt, int64_t n,
+                       ta_dtype dt, uint32_t flags, hipStream_t s) {
+  if (flags & ~uint32_t(TA_FLAG_TAN_GUARD)) return TA_EINVAL;
+  if (yt) {
+    void *o[3] = {ys, yc, yt};
+    if (flags & TA_FLAG_TAN_GUARD)
+      return fwd<kSin | kCos | kTan, true>(x, o, n, dt, s);
+    return fwd<kSin | kCos | kTan, false>(x, o, n, dt, s);
+  }
+  void *o[2] = {ys, yc};
+  return fwd<kSin | kCos, false>(x, o, n, dt, s);
+}
+
+ta_status ta_sincos(const void *x, void *ys, void *yc, void *yt, int64_t n,
+                    ta_dtype dt, hipStream_t s) {
+  return ta_sincos_ex(x, ys, yc, yt, n, dt, 0u, s);
+}
+
+ta_status ta_taylor_sin(const void *x, void *y, int64_t n, int terms,
+                        ta_dtype dt, hipStream_t s) {
+  return taylor<kSin>(x, y, n, terms, dt, s);
+}
+ta_status ta_taylor_cos(const void *x, void *y, int64_t n, int terms,
+                        ta_dtype dt, hipStream_t s) {
+  return taylor<kCos>(x, y, n, terms, dt, s);
+}
+ta_status ta_taylor_tan(const void *x, void *y, int64_t n, int terms,
+                        ta_dtype dt, hipStream_t s) {
+  return taylor<kTan>(x, y, n, terms, dt, s);
+}
+
+ta_status ta_sin_bwd(const void *x, const void *gy, void *gx, int64_t n,
+                     ta_dtype dt, hipStream_t s) {
+  return bwd<kSin, false>(x, gy, nullptr, gx, n, dt, s);
+}
+ta_status ta_cos_bwd(const void *x, const void *gy, void *gx, int64_t n,
+                     ta_dtype dt, hipStream_t s) {
+  return bwd<kCos, false>(x, gy, nullptr, gx, n, dt, s);
+}
+ta_status ta_tan_bwd(const void *x, const void *gy, void *gx, int64_t n,
+                     ta_dtype dt, hipStream_t s) {
+  return bwd<kTan, false>(x, gy, nullptr, gx, n, dt, s);
+}
+
+ta_status ta_sincos_bwd(const void *x, const void *gs, const void *gc,
+                        void *gx, int64_t n, ta_dtype dt, hipStream_t s) {
+  if (!dtype_ok(dt)) return TA_EDTYPE;
+  void *out[1] = {gx};
+  if (gs && gc) {
+    const void *in[3] = {x, gs, gc};
+    return run<SinCosBwdOp<true, true>>(in, out, n, dt, s);
+  }
+  if (gs) {
+    const void *in[2] = {x, gs};
+    return run<SinCosBwdOp<true, false>>(in, out, n, dt, s);
+  }
+  if (gc) {
+    const void *in[2] = {x, gc};
+    return run<SinCosBwdOp<false, true>>(in, out, n, dt, s);
+  }
+  return n < 0 || n > 0 ? TA_EINVAL : TA_OK;
+}
+
+ta_status ta_sin_fwdbwd(const void *x, const void *gy, void *y, void *gx,
+                        int64_t n, ta_dtype dt, hipStream_t s) {
+  return bwd<kSin, true>(x, gy, y, gx, n, dt, s);
+}
+ta_status ta_cos_fwdbwd(const void *x, const void *gy, void *y, void *gx,
+                        int64_t n, ta_dtype dt, hipStream_t s) {
+  return bwd<kCos, true>(x, gy, y, gx, n, dt, s);
+}
+ta_status ta_tan_fwdbwd(const void *x, const void *gy, void *y, void *gx,
+                        int64_t n, ta_dtype dt, hipStream_t s) {
+  return bwd<kTan, true>(x, gy, y, gx, n, dt, s);
+}
+
+ta_status ta_builtin_sincos(const void *x, void *ys, void *yc, void *yt,
+                            int64_t n, int kind, ta_dtype dt, hipStream_t s) {
+  if (!dtype_ok(dt)) return TA_EDTYPE;
+  if (dt != TA_F32) return TA_EDTYPE;
+  if (kind < 0 || kind > 2) return TA_EINVAL;
+  const void *in[1] = {x};
+  void *o3[3] = {ys, yc, yt};
+  if (yt) {
+    switch (kind) {
+      case 0: return run<BuiltinOp<0, true>>(in, o3, n, dt, s);
+      case 1: return run<BuiltinOp<1, true>>(in, o3, n, dt, s);
+      default: return run<BuiltinOp<2, true>>(in, o3, n, dt, s);
+    }
+  }
+  switch (kind) {
+    case 0: return run<BuiltinOp<0, false>>(in, o3, n, dt, s);
+    case 1: return run<BuiltinOp<1, false>>(in, o3, n, dt, s);
+    default: return run<BuiltinOp<2, false>>(in, o3, n, dt, s);
+  }
+}
+
+ta_status ta_copy(const void *const *in, int n_in, void *const *out, int n_out,
+                  int64_t n, ta_dtype dt, hipStream_t s) {
+  if (!dtype_ok(dt)) return TA_EDTYPE;
+  if (!in || !out || n_in < 1 || n_in > 3 || n_out < 1 || n_out > 3)
+    return TA_EINVAL;
+  switch (n_in * 4 + n_out) {
+    case 1 * 4 + 1: return run<CopyOp<1, 1>>(in, out, n, dt, s);
+    case 1 * 4 + 2: return run<CopyOp<1, 2>>(in, out, n, dt, s);
+    case 1 * 4 + 3: return run<CopyOp<1, 3>>(in, out, n, dt, s);
+    case 2 * 4 + 1: return run<CopyOp<2, 1>>(in, out, n, dt, s);
+    case 2 * 4 + 2: return run<CopyOp<2, 2>>(in, out, n, dt, s);
+    case 2 * 4 + 3: return run<CopyOp<2, 3>>(in, out, n, dt, s);
+    case 3 * 4 + 1: return run<CopyOp<3, 1>>(in, out, n, dt, s);
+    case 3 * 4 + 2: return run<CopyOp<3, 2>>(in, out, n, dt, s);
+    default: return run<CopyOp<3, 3>>(in, out, n, dt, s);
+  }
+}
+
+const char *ta_status_str(ta_status st) {
+  switch (st) {
+    case TA_OK: return "TA_OK";
+    case TA_EINVAL: return "TA_EINVAL: invalid argument";
+    case TA_EDTYPE: return "TA_EDTYPE: unsupported dtype";
+    case TA_EOVERLAP: return "TA_EOVERLAP: output partially overlaps another buffer";
+    case TA_EHIP: return "TA_EHIP: HIP launch failed";
+  }
+  return "unknown ta_status";
+}
+
+int ta_last_hip_error(void) { return g_last_hip_error; }
+
+const char *ta_version(void) { return "ta 0.1.0 (gfx950)"; }
+
+}  // extern "C"

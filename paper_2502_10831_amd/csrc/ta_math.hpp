@@ -1,0 +1,298 @@
+// ta_math.hpp -- per-element device arithmetic of the piecewise trigonometric
+// approximations (Goyal & Arora, arXiv 2502.10831) for gfx950.
+//
+// Split of the work (one element):
+//   1. Argument reduction, FP64.  x = q*(pi/2) + r, |r| <= pi/4 (FP64
+//      Cody-Waite with a two-word pi/2 below 2^29; a 2/pi bit-table reduction
+//      above).  a = |r| in degrees gives the piece inside [0, 45]; the parity
+//      of q says whether the fold angle is rho = a (q even) or its complement
+//      (q odd, rho = 90 - a degrees).  This is the Section 3 fold
+//      rho = arcsin|sin x|, with the sign of each output from (q mod 4, sign r).
+//   2. The piece's two linear forms N, D (Appendix A integer coefficients),
+//      FP64, each rounded once to FP32.  Pieces above 45 degrees are written
+//      in the complement variable, so D of the last piece is 11 * (90 - t)
+//      with no cancellation at the pole.  FP64 FMA issues at the same rate as
+//      unpacked FP32 FMA on gfx950, so this costs no more than an FP32
+//      reduction with a carried residual and rounds N and D only once.
+//   3. Everything after is FP32: Q = N^2 + D^2 (Appendix A.4), an inverse
+//      square root (v_rsq_f32 plus one Newton step whose residual is computed
+//      exactly with FMAs), sin = N*y, cos = D*y, and tan = N/D as a reciprocal
+//      plus one exact-residual correction.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ta {
+
+// ---------------------------------------------------------------------------
+// Constants.  Derived from pi with 400-bit mpmath arithmetic; a CPU test
+// re-derives each of them from this file's text.
+// ---------------------------------------------------------------------------
+constexpr double kTwoOverPi = 0x1.45f306dc9c883p-1;   // RN(2/pi)
+constexpr double kPio2Hi = 0x1.921fb54442d18p+0;      // RN(pi/2)
+constexpr double kPio2Lo = 0x1.1a62633145c07p-54;     // RN(pi/2 - kPio2Hi)
+constexpr double kDegPerRad = 0x1.ca5dc1a63c1f8p+5;   // RN(180/pi)
+constexpr double kRoundMagic = 0x1.8p52;              // 1.5 * 2^52
+constexpr float kLargeArg = 0x1p29f;  // |x| at and above: bit-table reduction
+
+// Bits 1..256 of the binary expansion of 2/pi, most significant first.
+__constant__ uint32_t kTwoOverPiBits[8] = {
+    0xA2F9836Eu, 0x4E441529u, 0xFC2757D1u, 0xF534DDC0u,
+    0xDB629599u, 0x3C439041u, 0xFE5163ABu, 0xDEBBC561u};
+
+// Appendix A integer forms, degrees: tan t ~ (a t + b) / (c t + d).
+// Piece 0: eq. (9); 1: eq. (5); 2: eq. (6); 3: eq. (7); 4: eq. (8);
+// 5: eq. (10).
+constexpr int kA[6] = {11, 10, 6, 10, 4, 1};
+constexpr int kB[6] = {0, 10, 46, 217, 297, 542};
+constexpr int kC[6] = {-1, -4, -5, -13, -10, -11};
+constexpr int kD[6] = {632, 657, 541, 1252, 910, 990};
+
+// Row `idx` = j + 3*(q & 1) of the per-element coefficient table, where j is
+// the 15-degree slot of a = |r| in [0, 45] degrees.  q even: rho = a, piece
+// k = j, N = b + a_k t, D = d + c_k t.  q odd: rho = 90 - a, piece k = 5 - j,
+// and with t = a (the complement) N = (90 a_k + b_k) - a_k t and
+// D = (90 c_k + d_k) - c_k t.
+struct PieceRow {
+  double iN, sN, iD, sD;  // N = iN + sN t, D = iD + sD t (t in degrees)
+};
+
+__host__ __device__ constexpr int piece_of_row(int idx) {
+  return idx < 3 ? idx : 5 - (idx - 3);
+}
+
+__host__ __device__ constexpr PieceRow piece_row(int idx) {
+  const int k = piece_of_row(idx);
+  return idx < 3 ? PieceRow{double(kB[k]), double(kA[k]), double(kD[k]),
+                            double(kC[k])}
+                 : PieceRow{double(90 * kA[k] + kB[k]), double(-kA[k]),
+                            double(90 * kC[k] + kD[k]), double(-kC[k])};
+}
+
+// (180/pi) * (a_k d_k - b_k c_k): d(tan piece)/d rho = this / D^2, and the
+// factor omega of d sin/d rho = omega cos is this / (N^2 + D^2).
+__host__ __device__ constexpr double kdet_of_row(int idx) {
+  const int k = piece_of_row(idx);
+  return kDegPerRad * double(kA[k] * kD[k] - kB[k] * kC[k]);
+}
+
+// Per-workgroup copy of the table in LDS (no table in HBM).
+struct Tables {
+  PieceRow row[6];
+  float kdet[6];
+};
+
+// One lane writes the table with immediates; the caller synchronises.
+__device__ inline void init_tables(Tables &tb) {
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      tb.row[i] = piece_row(i);
+      tb.kdet[i] = float(kdet_of_row(i));
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 1. Argument reduction
+// ---------------------------------------------------------------------------
+
+// |x| >= 2^29 (and +-Inf): x = m * 2^e exactly (m < 2^24, e in [6, 104]).
+// x*(2/pi) mod 4 needs only the 2/pi bits from 2^-(e-1) down; a 128-bit
+// window of them times m gives q mod 4 and the fraction to ~2^-96.
+__device__ inline void reduce_large(float x, double &r, uint32_t &q) {
+  const uint32_t ux = __float_as_uint(x);
+  const uint32_t ex = (ux >> 23) & 0xffu;
+  if (ex == 0xffu) {  // +-Inf (NaN never reaches here)
+    r = __builtin_nan("");
+    q = 0;
+    return;
+  }
+  const int e = int(ex) - 150;
+  const uint32_t m = (ux & 0x7fffffu) | 0x800000u;
+  const int i0 = e - 1;  // 1-based index of the first 2/pi bit needed
+  const int w0 = (i0 - 1) >> 5;
+  const int sh = (i0 - 1) & 31;
+  uint32_t w[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const uint64_t pair = (uint64_t(kTwoOverPiBits[w0 + k]) << 32) |
+                          kTwoOverPiBits[w0 + k + 1];
+    w[k] = uint32_t(pair >> (32 - sh));
+  }
+  // P = m * window mod 2^128, as four 32-bit words (p3 most significant).
+  const uint64_t a3 = uint64_t(m) * w[3], a2 = uint64_t(m) * w[2];
+  const uint64_t a1 = uint64_t(m) * w[1], a0 = uint64_t(m) * w[0];
+  uint64_t acc = (a3 >> 32) + (a2 & 0xffffffffu);
+  const uint32_t p1 = uint32_t(acc);
+  acc = (acc >> 32) + (a2 >> 32) + (a1 & 0xffffffffu);
+  const uint32_t p2 = uint32_t(acc);
+  acc = (acc >> 32) + (a1 >> 32) + (a0 & 0xffffffffu);
+  const uint32_t p3 = uint32_t(acc);
+  const uint32_t p0 = uint32_t(a3);
+  // x*(2/pi) mod 4 = P / 2^126: quadrant = top two bits, fraction below,
+  // rounded to nearest by reading the fraction as a signed 126-bit number.
+  const uint64_t top = (uint64_t(p3) << 34) | (uint64_t(p2) << 2) | (p1 >> 30);
+  const uint32_t nxt = (p1 << 2) | (p0 >> 30);
+  const int64_t stop = int64_t(top);
+  const double frac = double(stop) * 0x1p-64 + double(nxt) * 0x1p-96;
+  uint32_t qq = (p3 >> 30) + uint32_t(stop < 0 ? 1 : 0);
+  double rr = __builtin_fma(frac, kPio2Hi, frac * kPio2Lo);
+  if (ux >> 31) {
+    rr = -rr;
+    qq = 0u - qq;
+  }
+  r = rr;
+  q = qq;
+}
+
+// r and the low bits of q (two's complement) for any float x.
+__device__ inline void reduce(float x, double &r, uint32_t &q) {
+  const double xd = double(x);
+  const double qb = __builtin_fma(xd, kTwoOverPi, kRoundMagic);
+  const double qd = qb - kRoundMagic;  // +0 when q = 0, so r keeps x's zero
+  q = uint32_t(__double2loint(qb));    // low word of the mantissa = q
+  double rr = __builtin_fma(-qd, kPio2Hi, xd);  // exact
+  r = __builtin_fma(-qd, kPio2Lo, rr);
+  if (__builtin_expect(__builtin_fabsf(x) >= kLargeArg, 0)) reduce_large(x, r, q);
+}
+
+// Folded element: everything the later stages need.
+struct Folded {
+  double t;      // |r| in degrees, [0, 45]
+  double a;      // |r| in radians
+  uint32_t q;    // quadrant, low bits
+  uint32_t sr;   // sign bit of r
+  int idx;       // table row j + 3*(q & 1)
+};
+
+__device__ inline Folded fold(float x) {
+  double r;
+  uint32_t q;
+  reduce(x, r, q);
+  Folded f;
+  f.sr = uint32_t(__double2hiint(r)) >> 31;
+  f.a = __builtin_fabs(r);
+  f.t = f.a * kDegPerRad;
+  const int j = int(f.t >= 15.0) + int(f.t >= 30.0);
+  f.q = q;
+  f.idx = j + 3 * int(q & 1u);
+  return f;
+}
+
+// Sign bits (1 = negative) of sin, cos, tan for quadrant q and sign of r.
+__device__ inline uint32_t sin_sign(const Folded &f) {
+  return ((f.q & 1u) ? 0u : f.sr) ^ ((f.q >> 1) & 1u);
+}
+__device__ inline uint32_t cos_sign(const Folded &f) {
+  return ((f.q ^ (f.q >> 1)) & 1u) ^ ((f.q & 1u) ? f.sr : 0u);
+}
+__device__ inline uint32_t tan_sign(const Folded &f) {
+  return f.sr ^ (f.q & 1u);
+}
+__device__ inline float with_sign(float v, uint32_t neg) {
+  return __uint_as_float(__float_as_uint(v) ^ (neg << 31));
+}
+
+// ---------------------------------------------------------------------------
+// 2. Linear forms (FP64, rounded once)
+// ---------------------------------------------------------------------------
+struct Forms {
+  float n, d, q;  // N, D and Q = N^2 + D^2, each rounded once from FP64
+};
+
+__device__ inline Forms forms(const Folded &f, const Tables &tb) {
+  const PieceRow c = tb.row[f.idx];
+  const double nd = __builtin_fma(c.sN, f.t, c.iN);
+  const double dd = __builtin_fma(c.sD, f.t, c.iD);
+  const double qd = __builtin_fma(nd, nd, dd * dd);
+  return Forms{float(nd), float(dd), float(qd)};
+}
+
+// ---------------------------------------------------------------------------
+// 3. FP32 normalisation
+// ---------------------------------------------------------------------------
+
+// 1/sqrt(q): hardware estimate, then one Newton step y + (y/2)(1 - q y^2)
+// with 1 - q y^2 formed from the exact square y^2 = p + pe.
+__device__ inline float rsqrt_refined(float q) {
+  const float y = __builtin_amdgcn_rsqf(q);
+  const float p = y * y;
+  const float pe = __builtin_fmaf(y, y, -p);
+  float e = __builtin_fmaf(-q, p, 1.0f);
+  e = __builtin_fmaf(-q, pe, e);
+  return __builtin_fmaf(0.5f * y, e, y);
+}
+
+// n/d: reciprocal estimate, quotient, exact residual n - d*t0, correction.
+__device__ inline float div_refined(float n, float d) {
+  const float r = __builtin_amdgcn_rcpf(d);
+  const float t0 = n * r;
+  const float res = __builtin_fmaf(-d, t0, n);
+  return __builtin_fmaf(res, r, t0);
+}
+
+// 1/d refined by one Newton step.
+__device__ inline float rcp_refined(float d) {
+  const float r = __builtin_amdgcn_rcpf(d);
+  return __builtin_fmaf(__builtin_fmaf(-d, r, 1.0f), r, r);
+}
+
+// ---------------------------------------------------------------------------
+// Taylor baseline: first `TERMS` Maclaurin terms on the folded angle rho.
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr double factorial(int m) {
+  double f = 1.0;
+  for (int i = 2; i <= m; ++i) f *= double(i);
+  return f;
+}
+// tan^{(2j+1)}(0)/(2j+1)!: 1, 1/3, 2/15, 17/315, 62/2835, 1382/155925,
+// 21844/6081075, 929569/638512875, 6404582/10854718875.
+__host__ __device__ constexpr double tan_coef(int j) {
+  constexpr double num[9] = {1.0, 1.0, 2.0, 17.0, 62.0, 1382.0, 21844.0,
+                             929569.0, 6404582.0};
+  constexpr double den[9] = {1.0, 3.0, 15.0, 315.0, 2835.0, 155925.0,
+                             6081075.0, 638512875.0, 10854718875.0};
+  return num[j] / den[j];
+}
+__host__ __device__ constexpr float sin_coef(int j) {
+  return float(((j & 1) ? -1.0 : 1.0) / factorial(2 * j + 1));
+}
+__host__ __device__ constexpr float cos_coef(int j) {
+  return float(((j & 1) ? -1.0 : 1.0) / factorial(2 * j));
+}
+
+// rho in FP32 from the fold: a for even q, pi/2 - a for odd q.
+__device__ inline float fold_rho(const Folded &f) {
+  const double rho = (f.q & 1u) ? (kPio2Hi - f.a) + kPio2Lo : f.a;
+  return float(rho);
+}
+
+template <int TERMS>
+__device__ inline float taylor_sin_unsigned(float rho) {
+  const float z = rho * rho;
+  float s = sin_coef(TERMS - 1);
+#pragma unroll
+  for (int j = TERMS - 2; j >= 0; --j) s = __builtin_fmaf(s, z, sin_coef(j));
+  return s * rho;
+}
+template <int TERMS>
+__device__ inline float taylor_cos_unsigned(float rho) {
+  const float z = rho * rho;
+  float s = cos_coef(TERMS - 1);
+#pragma unroll
+  for (int j = TERMS - 2; j >= 0; --j) s = __builtin_fmaf(s, z, cos_coef(j));
+  return s;
+}
+template <int TERMS>
+__device__ inline float taylor_tan_unsigned(float rho) {
+  const float z = rho * rho;
+  float s = float(tan_coef(TERMS - 1));
+#pragma unroll
+  for (int j = TERMS - 2; j >= 0; --j)
+    s = __builtin_fmaf(s, z, float(tan_coef(j)));
+  return s * rho;
+}
+
+}  // namespace ta

@@ -1,0 +1,108 @@
+"""Parity rules used by the GPU tests (test infrastructure).
+
+FP32 outputs: |gpu - oracle| <= 4 ulp_f32(oracle), with
+    ulp_f32(y) = 2^(max(floor(log2|y|), -126) - 23),
+NaN where the oracle is NaN, an exact zero returned with the oracle's sign.
+
+Several-correct-results band: the approximation jumps at 15, 30, 60 and 75
+degrees, so an input whose fold angle lies within BAND rad of one of those
+nodes may legitimately be evaluated on either neighbouring piece; there the
+GPU value must be within the rule of one of the two pieces.
+
+16-bit outputs: the GPU value must be what rounding (RNE) some value within
+4 ulp_f32 of the oracle gives: RNE16(ref - tol) <= gpu <= RNE16(ref + tol).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+import oracle
+from paper_2502_10831_amd.workloads import decode_16, round_to_16
+
+BAND = 2.5e-7          # rad, ~2 FP32 ulp of pi/2
+U24 = 2.0 ** -24       # unit roundoff of FP32
+JUMP_NODES = np.array([1, 2, 4, 5]) * (math.pi / 12)
+
+
+def ulp32(y):
+    y = np.abs(np.asarray(y, np.float64))
+    with np.errstate(divide="ignore"):
+        e = np.floor(np.log2(np.where(y > 0, y, 1.0)))
+    e = np.where(y > 0, np.maximum(e, -126), -126)
+    return np.ldexp(1.0, (e - 23).astype(np.int64))
+
+
+def neighbour_values(x):
+    """For inputs near a jump node: the oracle's values on the piece across
+    the nearest node (signed like the outputs); NaN elsewhere."""
+    rho, v, k, ns, nc = oracle.fold(x)
+    d = np.abs(rho[:, None] - JUMP_NODES[None, :])
+    near = d.min(axis=1) < BAND
+    alt = {name: np.full(len(x), np.nan) for name in ("sin", "cos", "tan")}
+    for i in np.nonzero(near)[0]:
+        node = JUMP_NODES[np.argmin(d[i])]
+        k_alt = int(round(node / (math.pi / 12))) - (1 if rho[i] >= node else 0)
+        s, c, t = oracle.piece_scs(k_alt, rho[i], v[i])
+        alt["sin"][i] = -s if ns[i] else s
+        alt["cos"][i] = -c if nc[i] else c
+        alt["tan"][i] = -t if ns[i] != nc[i] else t
+    return near, alt
+
+
+def ulp_error(gpu, ref):
+    gpu = np.asarray(gpu, np.float64)
+    ref = np.asarray(ref, np.float64)
+    with np.errstate(invalid="ignore"):
+        return np.abs(gpu - ref) / ulp32(ref)
+
+
+def check_f32(name, x, gpu, ref, alt=None, near=None, max_ulp=4.0):
+    """Assert the FP32 rule; returns the max ulp error (band elements use the
+    better of the two pieces)."""
+    gpu = np.asarray(gpu, np.float64)
+    ref = np.asarray(ref, np.float64)
+    nan_ref = np.isnan(ref)
+    assert np.array_equal(np.isnan(gpu), nan_ref), \
+        f"{name}: NaN mismatch at {np.nonzero(np.isnan(gpu) != nan_ref)[0][:5]}"
+    err = ulp_error(gpu, ref)
+    err[nan_ref] = 0.0
+    if alt is not None and near is not None and near.any():
+        err_alt = ulp_error(gpu, alt[name])
+        err[near] = np.minimum(err[near], err_alt[near])
+    zero = (ref == 0) & ~nan_ref
+    if zero.any():
+        assert np.array_equal(np.signbit(gpu[zero]), np.signbit(ref[zero])), \
+            f"{name}: sign of zero differs"
+    worst = float(err.max()) if err.size else 0.0
+    if worst > max_ulp:
+        i = int(np.argmax(err))
+        raise AssertionError(
+            f"{name}: {worst:.3f} ulp > {max_ulp} at x={x[i]!r} "
+            f"gpu={gpu[i]!r} oracle={ref[i]!r}")
+    return worst
+
+
+def check_16(name, kind, gpu_raw, ref, tol_abs, alt=None, near=None):
+    """16-bit rule: gpu must equal RNE16(y) for some y in ref +- tol_abs
+    (or, in the band, around the neighbouring piece's value)."""
+    g = decode_16(gpu_raw, kind)
+    ref = np.asarray(ref, np.float64)
+    nan_ref = np.isnan(ref)
+    assert np.array_equal(np.isnan(g), nan_ref), f"{name}: NaN mismatch"
+
+    def ok_for(r):
+        lo = decode_16(round_to_16(r - tol_abs, kind), kind)
+        hi = decode_16(round_to_16(r + tol_abs, kind), kind)
+        with np.errstate(invalid="ignore"):
+            return (g >= lo) & (g <= hi)
+
+    ok = ok_for(ref) | nan_ref
+    if alt is not None and near is not None and near.any():
+        ok_alt = ok_for(np.where(near, alt[name], ref))
+        ok = ok | (near & ok_alt)
+    if not ok.all():
+        i = int(np.nonzero(~ok)[0][0])
+        raise AssertionError(f"{name}/{kind}: gpu={g[i]!r} oracle={ref[i]!r} "
+                             f"({(~ok).sum()} bad)")

@@ -1,0 +1,121 @@
+"""C ABI checks that need no GPU: the library loads, exports every symbol
+that include/ta.h declares, and rejects bad arguments before any HIP call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from conftest import ROOT
+
+LIB = os.path.join(ROOT, "paper_2502_10831_amd", "libta.so")
+HEADER = os.path.join(ROOT, "include", "ta.h")
+
+OK, EINVAL, EDTYPE, EOVERLAP, EHIP = range(5)
+F32, F16, BF16 = range(3)
+A, B = 0x100000, 0x200000   # fake device addresses: never dereferenced
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libta.so is not built (run __graft_entry__.build())")
+    return ctypes.CDLL(LIB)
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^(?:ta_status|const char \*|int)\s*(ta_\w+)\(",
+                                 text, re.M)))
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert len(names) >= 21
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def _fn(lib, name, *argtypes):
+    f = getattr(lib, name)
+    f.argtypes = list(argtypes)
+    f.restype = ctypes.c_int
+    return f
+
+
+vp, i64, i32, u32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_uint32
+
+
+def test_unary_validation(lib):
+    for name in ("ta_sin", "ta_cos", "ta_tan"):
+        f = _fn(lib, name, vp, vp, i64, i32, vp)
+        assert f(A, B, 16, 7, None) == EDTYPE
+        assert f(A, B, -1, F32, None) == EINVAL
+        assert f(None, B, 16, F32, None) == EINVAL
+        assert f(A, None, 16, F32, None) == EINVAL
+        assert f(A, A + 4, 16, F32, None) == EOVERLAP     # partial overlap
+        assert f(None, None, 0, F32, None) == OK          # n == 0: no launch
+        assert f(A, A - 2, 8, BF16, None) == EOVERLAP
+
+
+def test_sincos_validation(lib):
+    f = _fn(lib, "ta_sincos_ex", vp, vp, vp, vp, i64, i32, u32, vp)
+    assert f(A, B, None, None, 16, F32, 0, None) == EINVAL    # yc required
+    assert f(A, B, B + 32, None, 16, F32, 2, None) == EINVAL  # unknown flag
+    assert f(A, B, B + 32, B + 16, 16, F32, 0, None) == EOVERLAP
+    assert f(A, B, B, None, 16, F32, 0, None) == EOVERLAP     # ys == yc
+    assert f(A, B, B + 64, B + 128, 16, 3, 0, None) == EDTYPE
+    assert f(A, B, B + 64, None, 0, F32, 0, None) == OK
+    g = _fn(lib, "ta_tan_ex", vp, vp, i64, i32, u32, vp)
+    assert g(A, B, 16, F32, 4, None) == EINVAL
+
+
+def test_taylor_validation(lib):
+    for name in ("ta_taylor_sin", "ta_taylor_cos", "ta_taylor_tan"):
+        f = _fn(lib, name, vp, vp, i64, i32, i32, vp)
+        for bad in (0, 3, 4, 6, 8, 11):
+            assert f(A, B, 16, bad, F32, None) == EINVAL
+        assert f(A, B, 16, 5, 9, None) == EDTYPE
+        assert f(A, B, 0, 7, F32, None) == OK
+
+
+def test_backward_validation(lib):
+    for name in ("ta_sin_bwd", "ta_cos_bwd", "ta_tan_bwd"):
+        f = _fn(lib, name, vp, vp, vp, i64, i32, vp)
+        assert f(A, None, B, 16, F32, None) == EINVAL
+        assert f(A, B, A + 8, 16, F32, None) == EOVERLAP
+        assert f(A, B, B + 4, 16, F32, None) == EOVERLAP
+        assert f(A, B, None, 0, F32, None) == OK
+    f = _fn(lib, "ta_sincos_bwd", vp, vp, vp, vp, i64, i32, vp)
+    assert f(A, None, None, B, 16, F32, None) == EINVAL      # no gradient
+    assert f(A, None, None, B, 0, F32, None) == OK
+    assert f(A, B, None, None, 16, F32, None) == EINVAL
+    for name in ("ta_sin_fwdbwd", "ta_cos_fwdbwd", "ta_tan_fwdbwd"):
+        f = _fn(lib, name, vp, vp, vp, vp, i64, i32, vp)
+        assert f(A, B, None, B + 512, 16, F32, None) == EINVAL
+        assert f(A, B, B + 512, B + 520, 16, F32, None) == EOVERLAP
+        assert f(A, B, B + 512, B + 1024, 16, 5, None) == EDTYPE
+
+
+def test_comparator_validation(lib):
+    f = _fn(lib, "ta_builtin_sincos", vp, vp, vp, vp, i64, i32, i32, vp)
+    assert f(A, B, B + 256, None, 16, 0, F16, None) == EDTYPE
+    assert f(A, B, B + 256, None, 16, 3, F32, None) == EINVAL
+    c = _fn(lib, "ta_copy", ctypes.POINTER(vp), i32, ctypes.POINTER(vp), i32,
+            i64, i32, vp)
+    ins = (vp * 1)(A)
+    outs = (vp * 4)(B, B + 256, B + 512, B + 768)
+    assert c(ins, 0, outs, 1, 16, F32, None) == EINVAL
+    assert c(ins, 1, outs, 4, 16, F32, None) == EINVAL
+    assert c(ins, 1, outs, 1, 16, 9, None) == EDTYPE
+
+
+def test_status_strings(lib):
+    lib.ta_status_str.restype = ctypes.c_char_p
+    lib.ta_status_str.argtypes = [ctypes.c_int]
+    for s in range(5):
+        assert lib.ta_status_str(s).startswith(b"TA_")
+    lib.ta_version.restype = ctypes.c_char_p
+    assert b"gfx950" in lib.ta_version()
+    lib.ta_last_hip_error.restype = ctypes.c_int
+    assert lib.ta_last_hip_error() == 0

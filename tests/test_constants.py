@@ -1,0 +1,60 @@
+"""The GPU source's constants against first principles (CPU only): the
+reduction constants re-derived from pi with 400-bit mpmath, the 2/pi bit
+table, and the per-piece integers against the Appendix A forms printed in the
+paper."""
+import os
+import re
+
+import mpmath
+import pytest
+
+from conftest import ROOT, read_table
+
+SRC = os.path.join(ROOT, "paper_2502_10831_amd", "csrc", "ta_math.hpp")
+
+
+@pytest.fixture(scope="module")
+def text():
+    return open(SRC).read()
+
+
+def _const(text, name):
+    m = re.search(rf"constexpr double {name} = ([0-9a-fx.p+-]+);", text)
+    assert m, name
+    return float.fromhex(m.group(1))
+
+
+def test_reduction_constants(text):
+    mpmath.mp.prec = 400
+    pi = mpmath.pi
+    assert _const(text, "kTwoOverPi") == float(2 / pi)
+    hi = _const(text, "kPio2Hi")
+    assert hi == float(pi / 2)
+    assert _const(text, "kPio2Lo") == float(pi / 2 - mpmath.mpf(hi))
+    assert _const(text, "kDegPerRad") == float(180 / pi)
+    assert _const(text, "kRoundMagic") == 1.5 * 2.0 ** 52
+
+
+def test_two_over_pi_bits(text):
+    mpmath.mp.prec = 400
+    m = re.search(r"kTwoOverPiBits\[8\] = \{([^}]*)\}", text)
+    words = [int(w.strip().rstrip("u"), 16) for w in m.group(1).split(",")]
+    x = 2 / mpmath.pi
+    for w in words:
+        x *= 2 ** 32
+        top = int(mpmath.floor(x))
+        assert w == top
+        x -= top
+
+
+def test_piece_integers_match_appendix(text, golden_dir):
+    rows = read_table(os.path.join(golden_dir, "appendix_a_integer_forms.txt"))
+    arrays = {}
+    for name in ("kA", "kB", "kC", "kD"):
+        m = re.search(rf"constexpr int {name}\[6\] = \{{([^}}]*)\}}", text)
+        arrays[name] = [int(v) for v in m.group(1).split(",")]
+    for row in rows:
+        k = int(row[0])
+        a, b, c, d = (int(v) for v in row[4:8])
+        assert (arrays["kA"][k], arrays["kB"][k], arrays["kC"][k],
+                arrays["kD"][k]) == (a, b, c, d)

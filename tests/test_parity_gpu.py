@@ -1,0 +1,513 @@
+"""GPU parity: the HIP kernels (through the C ABI) against the FP64 oracle,
+element by element on seeded inputs.  Rules in tests/ta_check.py."""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2502_10831_amd as ta
+from paper_2502_10831_amd import workloads as wl
+from ta_check import (U24, check_16, check_f32, neighbour_values, ulp32,
+                      ulp_error)
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[gpu] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    ta.load()
+    return torch.device("cuda:0")
+
+
+def to_dev(a, dev, dtype=torch.float32):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev).view(dtype) \
+        if a.dtype == np.uint16 else torch.from_numpy(
+            np.ascontiguousarray(a)).to(dev)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def run_forward(x_dev):
+    """All forward entry points on one input; returns dict of numpy arrays."""
+    out = {}
+    for name, fn in (("sin", ta.ta_sin), ("cos", ta.ta_cos),
+                     ("tan", ta.ta_tan)):
+        y = torch.empty_like(x_dev)
+        fn(x_dev, y)
+        out[name] = host(y)
+    ys, yc, yt = (torch.empty_like(x_dev) for _ in range(3))
+    ta.ta_sincos(x_dev, ys, yc, yt)
+    out["f3_sin"], out["f3_cos"], out["f3_tan"] = host(ys), host(yc), host(yt)
+    ys2, yc2 = torch.empty_like(x_dev), torch.empty_like(x_dev)
+    ta.ta_sincos(x_dev, ys2, yc2, None)
+    out["f2_sin"], out["f2_cos"] = host(ys2), host(yc2)
+    return out
+
+
+def check_all_f32(x, out, label):
+    ref = oracle.forward(x.astype(np.float64))
+    near, alt = neighbour_values(x.astype(np.float64))
+    worst = {}
+    for key, name in (("sin", "sin"), ("cos", "cos"), ("tan", "tan"),
+                      ("f3_sin", "sin"), ("f3_cos", "cos"), ("f3_tan", "tan"),
+                      ("f2_sin", "sin"), ("f2_cos", "cos")):
+        if key in out:
+            worst[key] = check_f32(f"{label}:{key}", x, out[key], ref[name],
+                                   alt, near)
+    say(f"{label}: max ulp {worst}; band elements {int(near.sum())}")
+    return worst
+
+
+# ---------------------------------------------------------------------------
+# forward, FP32
+# ---------------------------------------------------------------------------
+
+def test_forward_small_uniform(dev):
+    n = (1 << 20) + 3   # several tiles and a ragged tail
+    say(f"forward small uniform n={n}")
+    x = wl.small_uniform(n)
+    out = run_forward(to_dev(x, dev))
+    check_all_f32(x, out, "U[-2pi,2pi]")
+    # the fused kernels compute bit-identical values to the single ones
+    for k in ("sin", "cos", "tan"):
+        assert np.array_equal(out[k].view(np.uint32),
+                              out["f3_" + k].view(np.uint32))
+
+
+def test_forward_strided_fp32_sweep(dev):
+    """Every 61st FP32 in [0, 2pi] and its negation (~18M values).  The full
+    sweep (every FP32 in [0, 2 pi]) runs with TA_EXHAUSTIVE=1."""
+    lo = np.float32(0.0).view(np.uint32)
+    hi = np.float32(2 * math.pi).view(np.uint32)
+    step = 1 if os.environ.get("TA_EXHAUSTIVE") == "1" else 61
+    chunk = 1 << 24
+    worst = {}
+    total = 0
+    for start in range(int(lo), int(hi) + 1, chunk * step):
+        bits = np.arange(start, min(start + chunk * step, int(hi) + 1), step,
+                         dtype=np.uint64).astype(np.uint32)
+        x = bits.view(np.float32)
+        x = np.concatenate([x, -x])
+        say(f"sweep chunk start=0x{start:08x} n={x.size}")
+        xd = to_dev(x, dev)
+        ys, yc, yt = (torch.empty_like(xd) for _ in range(3))
+        ta.ta_sincos(xd, ys, yc, yt)
+        out = {"f3_sin": host(ys), "f3_cos": host(yc), "f3_tan": host(yt)}
+        w = check_all_f32(x, out, "sweep")
+        for k, v in w.items():
+            worst[k] = max(worst.get(k, 0.0), v)
+        total += x.size
+    say(f"sweep total {total} values, max ulp {worst}")
+
+
+def test_forward_throughput_mix_full_size(dev):
+    """The benchmark workload (2^28 FP32, 1% near the poles) in the
+    benchmark's launch: sampled elements against the oracle, and the
+    identities S^2 + C^2 = 1, T = S/C on every element."""
+    n = 1 << 28
+    say(f"throughput mix n={n}: generating inputs")
+    x = wl.throughput_mix(n)
+    xd = to_dev(x, dev)
+    ys, yc, yt = (torch.empty_like(xd) for _ in range(3))
+    say("ta_sincos with tan")
+    ta.ta_sincos(xd, ys, yc, yt)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(7)
+    idx = rng.choice(n, 1 << 20, replace=False)
+    pole = np.nonzero(np.abs(np.cos(x.astype(np.float64))) < 2e-3)[0]
+    idx = np.unique(np.concatenate([idx, pole[:: max(1, pole.size // 200000)]]))
+    it = torch.from_numpy(idx).to(dev)
+    out = {"f3_sin": host(ys[it]), "f3_cos": host(yc[it]),
+           "f3_tan": host(yt[it])}
+    check_all_f32(x[idx], out, "mix-sampled")
+    s64, c64, t64 = ys.double(), yc.double(), yt.double()
+    # |S|,|C| <= 1 and each within 4 ulp of the formula: S^2 + C^2 - 1 is at
+    # most 2*(4+4) * 2^-24 in magnitude
+    dev_id = (s64 * s64 + c64 * c64 - 1.0).abs().max().item()
+    assert dev_id < 16 * U24, dev_id
+    rel = ((t64 - s64 / c64).abs() / (s64 / c64).abs().clamp_min(1e-30)).max()
+    assert rel.item() < 24 * U24, rel.item()
+    del s64, c64, t64
+
+
+def test_forward_log_magnitude(dev):
+    """|x| = 10^U[0,6]: the reduction of large arguments."""
+    n = 1 << 26
+    say(f"log magnitude n={n}")
+    x = wl.log_magnitude(n)
+    xd = to_dev(x, dev)
+    ys, yc, yt = (torch.empty_like(xd) for _ in range(3))
+    ta.ta_sincos(xd, ys, yc, yt)
+    torch.cuda.synchronize()
+    idx = np.random.default_rng(11).choice(n, 1 << 20, replace=False)
+    it = torch.from_numpy(idx).to(dev)
+    check_all_f32(x[idx], {"f3_sin": host(ys[it]), "f3_cos": host(yc[it]),
+                           "f3_tan": host(yt[it])}, "log-magnitude")
+
+
+def _closest_to_multiples_of_half_pi(count=64):
+    """FP32 values in (1, 2^20) closest to multiples of pi/2 (brute force
+    over the quotients, in FP64 then refined with the oracle's fold)."""
+    q = np.arange(1, 667544, dtype=np.float64)
+    c = q * (math.pi / 2)
+    f = c.astype(np.float32)
+    cand = np.concatenate([f, np.nextafter(f, np.float32(np.inf)),
+                           np.nextafter(f, np.float32(0))])
+    rho, v, _, _, _ = oracle.fold(cand.astype(np.float64))
+    d = np.minimum(rho, v)
+    return cand[np.argsort(d)[:count]]
+
+
+def test_forward_hard_inputs(dev):
+    """Worst-case reductions, node neighbourhoods, specials, subnormals."""
+    worst = _closest_to_multiples_of_half_pi()
+    nodes = (np.arange(-400, 400)[:, None] * (math.pi / 2) +
+             np.array([k * math.pi / 12 for k in range(1, 6)])[None, :]).ravel()
+    nf = nodes.astype(np.float32)
+    near_nodes = np.concatenate([nf, np.nextafter(nf, np.float32(np.inf)),
+                                 np.nextafter(nf, np.float32(-np.inf))])
+    specials = np.array([0.0, -0.0, np.inf, -np.inf, np.nan, 1e-45, -1e-45,
+                         1e-40, -3e-39, 1.1754942e-38, 1e-30, -1e-20,
+                         3.4028235e38, -3.4028235e38, 0.7853982, 0.7853981,
+                         1.5707964, 1.5707963, 3.1415927, 4.712389,
+                         252.898209, 2.0 ** 29, -(2.0 ** 29), 2.0 ** 29 - 32,
+                         1e6, -1e6], np.float32)
+    rng = np.random.default_rng(5)
+    big = rng.integers(0x4e000000, 0x7f800000, 200000,
+                       dtype=np.uint64).astype(np.uint32).view(np.float32)
+    big = np.concatenate([big, -big])
+    x = np.concatenate([worst, -worst, near_nodes, specials, big])
+    say(f"hard inputs n={x.size}")
+    out = run_forward(to_dev(x, dev))
+    check_all_f32(x, out, "hard")
+
+
+def test_alignment_tails_and_canaries(dev):
+    rng = np.random.default_rng(3)
+    base = rng.uniform(-50, 50, 5000).astype(np.float32)
+    ref = oracle.forward(base.astype(np.float64))
+    xd_all = to_dev(base, dev)
+    sentinel = 12345.0
+    for n in (0, 1, 2, 3, 4, 5, 7, 8, 9, 31, 33, 1023, 1025, 4097):
+        for xo in (0, 1, 2, 3):
+            for yo in (0, 1, 3):
+                say(f"align n={n} xoff={xo} yoff={yo}")
+                y_all = torch.full((n + 16,), sentinel, device=dev)
+                xs = xd_all[xo:xo + n]
+                ys = y_all[4 + yo:4 + yo + n]
+                ta.ta_sin(xs, ys)
+                y = host(y_all)
+                assert np.all(y[:4 + yo] == sentinel)
+                assert np.all(y[4 + yo + n:] == sentinel)
+                if n:
+                    err = ulp_error(y[4 + yo:4 + yo + n], ref["sin"][xo:xo + n])
+                    assert err.max() <= 4.0
+
+
+def test_in_place(dev):
+    x = wl.small_uniform(10001, seed=9)
+    ref = oracle.forward(x.astype(np.float64))
+    for name, fn in (("sin", ta.ta_sin), ("cos", ta.ta_cos),
+                     ("tan", ta.ta_tan)):
+        say(f"in place {name}")
+        xd = to_dev(x, dev)
+        fn(xd, xd)
+        assert ulp_error(host(xd), ref[name]).max() <= 4.0
+
+
+def test_tan_guard(dev):
+    x = wl.throughput_mix(1 << 16, seed=13)
+    xd = to_dev(x, dev)
+    say("tan guard")
+    y0, y1 = torch.empty_like(xd), torch.empty_like(xd)
+    ta.ta_tan_ex(xd, y0, 0)
+    ta.ta_tan_ex(xd, y1, ta.TA_FLAG_TAN_GUARD)
+    ref = oracle.forward(x.astype(np.float64), flags=oracle.TAN_GUARD)["tan"]
+    g0, g1 = host(y0), host(y1)
+    guarded = np.isinf(ref)
+    assert guarded.sum() > 100
+    assert np.all(np.isposinf(g1[guarded]))
+    assert np.array_equal(g1[~guarded].view(np.uint32),
+                          g0[~guarded].view(np.uint32))
+    ys, yc, yt = (torch.empty_like(xd) for _ in range(3))
+    ta.ta_sincos_ex(xd, ys, yc, yt, ta.TA_FLAG_TAN_GUARD)
+    assert np.array_equal(host(yt).view(np.uint32), g1.view(np.uint32))
+
+
+# ---------------------------------------------------------------------------
+# forward, 16-bit storage: every pattern
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("kind", ["f16", "bf16"])
+def test_forward_16bit_exhaustive(dev, kind):
+    tdt = torch.float16 if kind == "f16" else torch.bfloat16
+    raw = wl.all_16bit_patterns()
+    x64 = wl.decode_16(raw, kind)
+    say(f"16-bit exhaustive {kind}")
+    xd = torch.from_numpy(raw.view(np.int16)).to(dev).view(tdt)
+    ref = oracle.forward(x64)
+    near, alt = neighbour_values(x64)
+    outs = {}
+    for name, fn in (("sin", ta.ta_sin), ("cos", ta.ta_cos),
+                     ("tan", ta.ta_tan)):
+        y = torch.empty_like(xd)
+        fn(xd, y)
+        outs[name] = host(y.view(torch.int16)).view(np.uint16)
+    ys, yc, yt = (torch.empty_like(xd) for _ in range(3))
+    ta.ta_sincos(xd, ys, yc, yt)
+    for name, t in (("sin", ys), ("cos", yc), ("tan", yt)):
+        fused = host(t.view(torch.int16)).view(np.uint16)
+        assert np.array_equal(fused, outs[name])
+        check_16(name, kind, outs[name], ref[name], 4 * ulp32(ref[name]),
+                 alt, near)
+
+
+@pytest.mark.parametrize("kind", ["f16", "bf16"])
+def test_forward_16bit_full_size(dev, kind):
+    """2^29 16-bit inputs U[-pi, pi] in the benchmark launch: every output
+    equals the exhaustive table entry of its input pattern."""
+    tdt = torch.float16 if kind == "f16" else torch.bfloat16
+    table_in = torch.from_numpy(
+        wl.all_16bit_patterns().view(np.int16)).to(dev).view(tdt)
+    tabs, tabc, tabt = (torch.empty_like(table_in) for _ in range(3))
+    ta.ta_sincos(table_in, tabs, tabc, tabt)
+    n = 1 << 29
+    say(f"16-bit full size {kind} n={n}")
+    gen = torch.Generator(device=dev).manual_seed(wl.SEED)
+    x = (torch.rand(n, device=dev, generator=gen, dtype=torch.float64)
+         * (2 * math.pi) - math.pi).to(tdt)
+    ys, yc, yt = (torch.empty_like(x) for _ in range(3))
+    ta.ta_sincos(x, ys, yc, yt)
+    idx = x.view(torch.int16).long() & 0xFFFF
+    for out, tab in ((ys, tabs), (yc, tabc), (yt, tabt)):
+        expect = tab.view(torch.int16)[idx]
+        assert torch.equal(out.view(torch.int16), expect)
+    torch.cuda.synchronize()
+
+
+# ---------------------------------------------------------------------------
+# Taylor baseline
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("terms", [5, 7, 9])
+def test_taylor(dev, terms):
+    x = wl.small_uniform((1 << 18) + 5, seed=21)
+    xd = to_dev(x, dev)
+    say(f"taylor terms={terms}")
+    ref = oracle.taylor(x.astype(np.float64), terms)
+    for name, fn in (("sin", ta.ta_taylor_sin), ("cos", ta.ta_taylor_cos),
+                     ("tan", ta.ta_taylor_tan)):
+        y = torch.empty_like(xd)
+        fn(xd, y, terms)
+        g = host(y).astype(np.float64)
+        # FP32 Horner on rho^2 with rho rounded once: error bound
+        # (4N + 2) u * sum|terms|  (u = 2^-24), plus the output rounding
+        tol = (4 * terms + 2) * U24 * ref["abs_" + name] + ulp32(ref[name])
+        bad = np.abs(g - ref[name]) > tol
+        assert not bad.any(), (name, x[bad][:3], g[bad][:3], ref[name][bad][:3])
+
+
+# ---------------------------------------------------------------------------
+# backward and fused forward+backward
+# ---------------------------------------------------------------------------
+
+GRAD_ULPS = 12  # derivation: omega (4 roundings) x output (2.5 ulp) x g
+
+
+def _grad_case(n, sigma, seed):
+    x, g = wl.normal_pair((n,), sigma, seed=seed)
+    return x, g
+
+
+def _check_grad(name, x, g, gx, ref_grad, scale):
+    ref = g.astype(np.float64) * ref_grad
+    tol = GRAD_ULPS * U24 * scale + ulp32(ref)
+    near, _ = neighbour_values(x.astype(np.float64))
+    bad = (np.abs(gx.astype(np.float64) - ref) > tol) & ~near
+    assert not bad.any(), (name, x[bad][:3], gx[bad][:3], ref[bad][:3])
+
+
+def test_backward_f32(dev):
+    n = (1 << 20) + 7
+    x, g = _grad_case(n, 3.0, 31)
+    say(f"backward f32 n={n}")
+    xd, gd = to_dev(x, dev), to_dev(g, dev)
+    rg = oracle.grad(x.astype(np.float64))
+    rf = oracle.forward(x.astype(np.float64))
+    g64 = g.astype(np.float64)
+    for name, bwd, fb in (("sin", ta.ta_sin_bwd, ta.ta_sin_fwdbwd),
+                          ("cos", ta.ta_cos_bwd, ta.ta_cos_fwdbwd),
+                          ("tan", ta.ta_tan_bwd, ta.ta_tan_fwdbwd)):
+        gx = torch.empty_like(xd)
+        bwd(xd, gd, gx)
+        gxh = host(gx)
+        _check_grad(name, x, g, gxh, rg[name], np.abs(g64 * rg[name]))
+        y2, gx2 = torch.empty_like(xd), torch.empty_like(xd)
+        fb(xd, gd, y2, gx2)
+        assert np.array_equal(host(gx2).view(np.uint32), gxh.view(np.uint32))
+        near, alt = neighbour_values(x.astype(np.float64))
+        check_f32(f"fwdbwd-y:{name}", x, host(y2), rf[name], alt, near)
+    # sincos backward: gx = gs dsin + gc dcos
+    gs, gc = g, wl.normal_pair((n,), 1.0, seed=32)[1]
+    gsd, gcd = to_dev(gs, dev), to_dev(gc, dev)
+    scale = np.abs(gs * rg["sin"]) + np.abs(gc * rg["cos"])
+    for label, a, b, ref in (
+            ("both", gsd, gcd, gs * rg["sin"] + gc * rg["cos"]),
+            ("gs", gsd, None, gs * rg["sin"]),
+            ("gc", None, gcd, gc * rg["cos"])):
+        gx = torch.empty_like(xd)
+        ta.ta_sincos_bwd(xd, a, b, gx)
+        near, _ = neighbour_values(x.astype(np.float64))
+        tol = GRAD_ULPS * U24 * scale + ulp32(ref)
+        bad = (np.abs(host(gx) - ref) > tol) & ~near
+        assert not bad.any(), (label, x[bad][:3])
+
+
+@pytest.mark.parametrize("kind", ["f16", "bf16"])
+def test_backward_16bit(dev, kind):
+    tdt = torch.float16 if kind == "f16" else torch.bfloat16
+    n = 1 << 16
+    x, g = _grad_case(n, 3.0, 41)
+    xr, gr = wl.round_to_16(x, kind), wl.round_to_16(g, kind)
+    x64, g64 = wl.decode_16(xr, kind), wl.decode_16(gr, kind)
+    say(f"backward {kind}")
+    xd = torch.from_numpy(xr.view(np.int16)).to(dev).view(tdt)
+    gd = torch.from_numpy(gr.view(np.int16)).to(dev).view(tdt)
+    rg = oracle.grad(x64)
+    near, _ = neighbour_values(x64)
+    for name, bwd in (("sin", ta.ta_sin_bwd), ("cos", ta.ta_cos_bwd),
+                      ("tan", ta.ta_tan_bwd)):
+        gx = torch.empty_like(xd)
+        bwd(xd, gd, gx)
+        raw = host(gx.view(torch.int16)).view(np.uint16)
+        ref = g64 * rg[name]
+        tol = GRAD_ULPS * U24 * np.abs(ref) + ulp32(ref)
+        bad_free = ~near
+        check_16(f"bwd-{name}", kind, raw[bad_free], ref[bad_free],
+                 tol[bad_free])
+
+
+def test_gradient_vs_finite_differences_and_trig(dev):
+    """Central differences of the FP64 oracle (h = 1e-3) at 10^4 points away
+    from the piece boundaries; and the distance to the exact-trig gradient."""
+    rng = np.random.default_rng(51)
+    x = (rng.standard_normal(40000) * 3.0).astype(np.float32)
+    h = 1e-3
+    x64 = x.astype(np.float64)
+    rho, v, _, _, _ = oracle.fold(x64)
+    nodes = np.arange(1, 6) * (math.pi / 12)
+    dist = np.abs(rho[:, None] - nodes[None, :]).min(axis=1)
+    keep = (dist > 2 * h) & (v > 2 * h)
+    x = x[keep][:10000]
+    x64 = x.astype(np.float64)
+    say(f"finite differences n={x.size}")
+    xd = to_dev(x, dev)
+    ones = torch.ones_like(xd)
+    fp = oracle.forward(x64 + h)
+    fm = oracle.forward(x64 - h)
+    t0 = oracle.forward(x64)["tan"]
+    for name, bwd in (("sin", ta.ta_sin_bwd), ("cos", ta.ta_cos_bwd),
+                      ("tan", ta.ta_tan_bwd)):
+        gx = torch.empty_like(xd)
+        bwd(xd, ones, gx)
+        gpu = host(gx).astype(np.float64)
+        fd = (fp[name] - fm[name]) / (2 * h)
+        # central-difference truncation h^2/6 |f'''| with the trig third
+        # derivative as the size (sin/cos: <= 1.1; tan: 2 sec^2 (3 tan^2 + 1))
+        if name == "tan":
+            sec2 = 1.0 + t0 * t0
+            trunc = h * h / 6 * 2 * sec2 * (3 * t0 * t0 + 1) * 1.5
+            keep_t = np.abs(t0) < 20.0
+        else:
+            trunc = np.full_like(fd, h * h / 6 * 1.1 * 1.5)
+            keep_t = np.ones_like(fd, bool)
+        tol = 1e-5 + 8 * ulp32(fd) + trunc + 2 * GRAD_ULPS * U24 * np.abs(fd)
+        bad = (np.abs(gpu - fd) > tol) & keep_t
+        assert not bad.any(), (name, x[bad][:3], gpu[bad][:3], fd[bad][:3])
+    gx = torch.empty_like(xd)
+    ta.ta_sin_bwd(xd, ones, gx)
+    d = np.abs(host(gx).astype(np.float64) - np.cos(x64))
+    say(f"|d sin_a/dx - cos x|: max {d.max():.4g} mean {d.mean():.4g}")
+    assert d.max() < 2.3e-2
+
+
+def test_autograd_functions(dev):
+    x, g = _grad_case(4099, 3.0, 61)
+    xd = to_dev(x, dev).requires_grad_(True)
+    gd = to_dev(g, dev)
+    say("autograd functions")
+    for fn, bwd, fwd in ((ta.SinFn, ta.ta_sin_bwd, ta.ta_sin),
+                         (ta.CosFn, ta.ta_cos_bwd, ta.ta_cos),
+                         (ta.TanFn, ta.ta_tan_bwd, ta.ta_tan)):
+        xd.grad = None
+        y = fn.apply(xd)
+        y.backward(gd)
+        yref, gref = torch.empty_like(gd), torch.empty_like(gd)
+        fwd(xd.detach(), yref)
+        bwd(xd.detach(), gd, gref)
+        assert torch.equal(y.detach(), yref)
+        assert torch.equal(xd.grad, gref)
+    xd.grad = None
+    s, c = ta.SinCosFn.apply(xd)
+    (s * gd + c * 2.0).sum().backward()
+    gref = torch.empty_like(gd)
+    ta.ta_sincos_bwd(xd.detach(), gd, torch.full_like(gd, 2.0), gref)
+    assert torch.equal(xd.grad, gref)
+
+
+def test_fused_fwdbwd_full_size(dev):
+    """[128, 8192, 512] FP32 activation, x ~ N(0, 10^2): the fused kernel in
+    the benchmark launch, sampled against the oracle."""
+    shape = (128, 8192, 512)
+    n = int(np.prod(shape))
+    say(f"fused fwd+bwd full size n={n}: generating")
+    gen = torch.Generator(device=dev).manual_seed(wl.SEED)
+    x = torch.randn(n, device=dev, generator=gen) * 10.0
+    g = torch.randn(n, device=dev, generator=gen)
+    y, gx = torch.empty_like(x), torch.empty_like(x)
+    ta.ta_sin_fwdbwd(x, g, y, gx)
+    torch.cuda.synchronize()
+    idx = torch.from_numpy(
+        np.random.default_rng(71).choice(n, 1 << 20, replace=False)).to(dev)
+    xs, gs = host(x[idx]), host(g[idx])
+    ys, gxs = host(y[idx]), host(gx[idx])
+    ref_f = oracle.forward(xs.astype(np.float64))
+    near, alt = neighbour_values(xs.astype(np.float64))
+    check_f32("fwdbwd-y", xs, ys, ref_f["sin"], alt, near)
+    rg = oracle.grad(xs.astype(np.float64))
+    _check_grad("fwdbwd-gx", xs, gs, gxs, rg["sin"],
+                np.abs(gs.astype(np.float64) * rg["sin"]))
+    del x, g, y, gx
+
+
+# ---------------------------------------------------------------------------
+# comparators and the copy ceiling kernel (not the method)
+# ---------------------------------------------------------------------------
+
+def test_comparators_and_copy(dev):
+    x = wl.small_uniform(1 << 16, seed=81)
+    xd = to_dev(x, dev)
+    say("comparators")
+    x64 = x.astype(np.float64)
+    for kind, tol in ((0, 4e-7), (1, 2e-3), (2, 4e-7)):
+        ys, yc, yt = (torch.empty_like(xd) for _ in range(3))
+        ta.ta_builtin_sincos(xd, ys, yc, yt, kind=kind)
+        assert np.abs(host(ys) - np.sin(x64)).max() < tol
+        assert np.abs(host(yc) - np.cos(x64)).max() < tol
+    outs = [torch.empty_like(xd) for _ in range(3)]
+    ta.ta_copy([xd], outs)
+    for o in outs:
+        assert torch.equal(o, xd)
