@@ -2,10 +2,10 @@
 //
 // Every entry point is an elementwise map: NIN input streams, NOUT output
 // streams, one functor per element.  The streaming skeleton issues 16-byte
-// global loads and stores (4 FP32 or 8 16-bit elements per access), UNROLL
-// accesses per stream per thread with all loads issued before any compute,
-// 256-thread workgroups, and 64-bit indexing.  The per-piece coefficients
-// live in LDS (one 200-byte copy per workgroup), never in HBM.
+// global loads and stores (4 FP32 or 8 16-bit elements per access), with a
+// launch shape per kernel category (see shape_for) and 64-bit indexing.  The
+// per-piece coefficients live in LDS (one 200-byte copy per workgroup),
+// never in HBM.
 #include <hip/hip_runtime.h>
 #include <hip/hip_fp16.h>
 #include <stdint.h>
@@ -15,8 +15,6 @@
 #include "ta_math.hpp"
 
 namespace ta {
-
-constexpr int kBlock = 256;
 
 // ---------------------------------------------------------------------------
 // Storage formats.  Loads widen exactly to FP32; stores round to nearest
@@ -198,6 +196,53 @@ struct Vec {
   static constexpr int kElems = 16 / int(sizeof(typename ST::raw));
 };
 
+// Launch shape of the vector body, per kernel category, chosen by timing on
+// MI355X (2^28-2^29 elements):
+//   one input, several FP32 outputs: 256 threads, one 16-byte access per
+//     stream per thread, nontemporal stores;
+//   one output, or 16-bit storage (VALU-bound): two accesses per thread;
+//   two or more inputs (backward, fused forward+backward): 128 threads, one
+//     access, nontemporal loads and stores.
+// The TA_SHAPE_* macros exist only to re-time alternatives at build time.
+struct Shape {
+  int block, unroll;
+  bool nt_load, nt_store;
+};
+#ifndef TA_SHAPE_MULTI
+#define TA_SHAPE_MULTI {256, 1, false, true}
+#endif
+#ifndef TA_SHAPE_SINGLE
+#define TA_SHAPE_SINGLE {256, 2, false, true}
+#endif
+#ifndef TA_SHAPE_TWOIN
+#define TA_SHAPE_TWOIN {128, 1, true, true}
+#endif
+
+template <class ST, class Op>
+constexpr Shape shape_for() {
+  if (Op::NIN >= 2) return Shape TA_SHAPE_TWOIN;
+  if (Op::NOUT >= 2 && sizeof(typename ST::raw) == 4) return Shape TA_SHAPE_MULTI;
+  return Shape TA_SHAPE_SINGLE;
+}
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+template <bool NT>
+__device__ inline u32x4 vload(const char *base, int64_t v) {
+  const u32x4 *p = reinterpret_cast<const u32x4 *>(base) + v;
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  return *p;
+}
+template <bool NT>
+__device__ inline void vstore(char *base, int64_t v, u32x4 x) {
+  u32x4 *p = reinterpret_cast<u32x4 *>(base) + v;
+  if constexpr (NT) {
+    __builtin_nontemporal_store(x, p);
+  } else {
+    *p = x;
+  }
+}
+
 template <class ST, class Op>
 __device__ inline void scalar_element(const IoPtrs &io, int64_t i,
                                       const Tables &tb) {
@@ -212,11 +257,13 @@ __device__ inline void scalar_element(const IoPtrs &io, int64_t i,
     reinterpret_cast<raw *>(io.out[k])[i] = ST::store(out[k]);
 }
 
-// Vector body: elements [head, head + nvec*VEC) in 16-byte accesses; block 0
-// also does the scalar head [0, head) and tail [head + nvec*VEC, n).
-template <class ST, class Op, int UNROLL>
-__global__ __launch_bounds__(kBlock) void map_vec_kernel(IoPtrs io, int64_t head,
-                                                         int64_t nvec, int64_t n) {
+// Vector body: elements [head, head + nvec*VEC) in 16-byte accesses, UNROLL
+// accesses per stream per thread, all loads issued before any compute.  The
+// workgroup with blockIdx 0 also does the scalar head [0, head) and tail
+// [head + nvec*VEC, n).
+template <class ST, class Op, int BLOCK, int UNROLL, bool NTL, bool NTS>
+__global__ __launch_bounds__(BLOCK) void map_vec_kernel(IoPtrs io, int64_t head,
+                                                        int64_t nvec, int64_t n) {
   using raw = typename ST::raw;
   constexpr int VEC = Vec<ST>::kElems;
   __shared__ Tables tb;
@@ -224,23 +271,29 @@ __global__ __launch_bounds__(kBlock) void map_vec_kernel(IoPtrs io, int64_t head
     init_tables(tb);
     __syncthreads();
   }
-  const int64_t v0 = int64_t(blockIdx.x) * (UNROLL * kBlock) + threadIdx.x;
-  uint4 in_raw[UNROLL][Op::NIN];
+  const int64_t v0 = int64_t(blockIdx.x) * (UNROLL * BLOCK) + threadIdx.x;
+  const char *in_base[Op::NIN];
+  char *out_base[Op::NOUT];
+#pragma unroll
+  for (int k = 0; k < Op::NIN; ++k)
+    in_base[k] = io.in[k] + head * int64_t(sizeof(raw));
+#pragma unroll
+  for (int k = 0; k < Op::NOUT; ++k)
+    out_base[k] = io.out[k] + head * int64_t(sizeof(raw));
+  u32x4 in_raw[UNROLL][Op::NIN];
 #pragma unroll
   for (int u = 0; u < UNROLL; ++u) {
-    const int64_t v = v0 + int64_t(u) * kBlock;
+    const int64_t v = v0 + int64_t(u) * BLOCK;
     if (v < nvec) {
 #pragma unroll
-      for (int k = 0; k < Op::NIN; ++k)
-        in_raw[u][k] = reinterpret_cast<const uint4 *>(
-            io.in[k] + head * int64_t(sizeof(raw)))[v];
+      for (int k = 0; k < Op::NIN; ++k) in_raw[u][k] = vload<NTL>(in_base[k], v);
     }
   }
 #pragma unroll
   for (int u = 0; u < UNROLL; ++u) {
-    const int64_t v = v0 + int64_t(u) * kBlock;
+    const int64_t v = v0 + int64_t(u) * BLOCK;
     if (v < nvec) {
-      uint4 out_raw[Op::NOUT];
+      u32x4 out_raw[Op::NOUT];
 #pragma unroll
       for (int e = 0; e < VEC; ++e) {
         float in[Op::NIN], out[Op::NOUT];
@@ -253,43 +306,38 @@ __global__ __launch_bounds__(kBlock) void map_vec_kernel(IoPtrs io, int64_t head
           reinterpret_cast<raw *>(&out_raw[k])[e] = ST::store(out[k]);
       }
 #pragma unroll
-      for (int k = 0; k < Op::NOUT; ++k)
-        reinterpret_cast<uint4 *>(io.out[k] + head * int64_t(sizeof(raw)))[v] =
-            out_raw[k];
+      for (int k = 0; k < Op::NOUT; ++k) vstore<NTS>(out_base[k], v, out_raw[k]);
     }
   }
   if (blockIdx.x == 0) {
     const int64_t tail0 = head + nvec * VEC;
     const int64_t extra = head + (n - tail0);
-    for (int64_t e = threadIdx.x; e < extra; e += kBlock)
+    for (int64_t e = threadIdx.x; e < extra; e += BLOCK)
       scalar_element<ST, Op>(io, e < head ? e : tail0 + (e - head), tb);
   }
 }
 
 // Fallback when the buffers disagree on their address modulo 16.
+constexpr int kScalarBlock = 256;
 template <class ST, class Op>
-__global__ __launch_bounds__(kBlock) void map_scalar_kernel(IoPtrs io, int64_t n) {
+__global__ __launch_bounds__(kScalarBlock) void map_scalar_kernel(IoPtrs io,
+                                                                  int64_t n) {
   __shared__ Tables tb;
   if constexpr (Op::kNeedsTables) {
     init_tables(tb);
     __syncthreads();
   }
-  const int64_t stride = int64_t(gridDim.x) * kBlock;
-  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride)
+  const int64_t stride = int64_t(gridDim.x) * kScalarBlock;
+  for (int64_t i = int64_t(blockIdx.x) * kScalarBlock + threadIdx.x; i < n;
+       i += stride)
     scalar_element<ST, Op>(io, i, tb);
 }
-
-template <class Op>
-struct Unroll {
-  static constexpr int value = 2;
-};
 
 template <class ST, class Op>
 hipError_t launch_map(const void *const *in, void *const *out, int64_t n,
                       hipStream_t stream) {
   using raw = typename ST::raw;
   constexpr int VEC = Vec<ST>::kElems;
-  constexpr int UNROLL = Unroll<Op>::value;
   IoPtrs io{};
   const uintptr_t mis = uintptr_t(in[0]) & 15u;
   bool same = (mis % sizeof(raw)) == 0;
@@ -305,16 +353,19 @@ hipError_t launch_map(const void *const *in, void *const *out, int64_t n,
     int64_t head = mis ? int64_t((16u - mis) / sizeof(raw)) : 0;
     if (head > n) head = n;
     const int64_t nvec = (n - head) / VEC;
-    const int64_t per_block = int64_t(UNROLL) * kBlock;
+    constexpr Shape sh = shape_for<ST, Op>();
+    const int64_t per_block = int64_t(sh.unroll) * sh.block;
     int64_t blocks = (nvec + per_block - 1) / per_block;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL((map_vec_kernel<ST, Op, UNROLL>), dim3(unsigned(blocks)),
-                       dim3(kBlock), 0, stream, io, head, nvec, n);
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(
+        (map_vec_kernel<ST, Op, sh.block, sh.unroll, sh.nt_load, sh.nt_store>),
+        dim3(unsigned(blocks)), dim3(sh.block), 0, stream, io, head, nvec, n);
   } else {
-    int64_t blocks = (n + kBlock - 1) / kBlock;
+    int64_t blocks = (n + kScalarBlock - 1) / kScalarBlock;
     if (blocks > 65536) blocks = 65536;
     hipLaunchKernelGGL((map_scalar_kernel<ST, Op>), dim3(unsigned(blocks)),
-                       dim3(kBlock), 0, stream, io, n);
+                       dim3(kScalarBlock), 0, stream, io, n);
   }
   return hipGetLastError();
 }

@@ -60,7 +60,8 @@ def ulp_error(gpu, ref):
 
 def check_f32(name, x, gpu, ref, alt=None, near=None, max_ulp=4.0):
     """Assert the FP32 rule; returns the max ulp error (band elements use the
-    better of the two pieces)."""
+    better of the two pieces).  `name` is 'label:fn' or 'fn' with fn one of
+    sin/cos/tan."""
     gpu = np.asarray(gpu, np.float64)
     ref = np.asarray(ref, np.float64)
     nan_ref = np.isnan(ref)
@@ -69,7 +70,7 @@ def check_f32(name, x, gpu, ref, alt=None, near=None, max_ulp=4.0):
     err = ulp_error(gpu, ref)
     err[nan_ref] = 0.0
     if alt is not None and near is not None and near.any():
-        err_alt = ulp_error(gpu, alt[name])
+        err_alt = ulp_error(gpu, alt[name.rsplit(":", 1)[-1].split("_")[-1]])
         err[near] = np.minimum(err[near], err_alt[near])
     zero = (ref == 0) & ~nan_ref
     if zero.any():
@@ -86,7 +87,8 @@ def check_f32(name, x, gpu, ref, alt=None, near=None, max_ulp=4.0):
 
 def check_16(name, kind, gpu_raw, ref, tol_abs, alt=None, near=None):
     """16-bit rule: gpu must equal RNE16(y) for some y in ref +- tol_abs
-    (or, in the band, around the neighbouring piece's value)."""
+    (or, in the band, around the neighbouring piece's value).  `name` ends
+    with the function name (sin/cos/tan)."""
     g = decode_16(gpu_raw, kind)
     ref = np.asarray(ref, np.float64)
     nan_ref = np.isnan(ref)
@@ -100,7 +102,8 @@ def check_16(name, kind, gpu_raw, ref, tol_abs, alt=None, near=None):
 
     ok = ok_for(ref) | nan_ref
     if alt is not None and near is not None and near.any():
-        ok_alt = ok_for(np.where(near, alt[name], ref))
+        fn = name.rsplit("-", 1)[-1].rsplit(":", 1)[-1]
+        ok_alt = ok_for(np.where(near, alt[fn], ref))
         ok = ok | (near & ok_alt)
     if not ok.all():
         i = int(np.nonzero(~ok)[0][0])

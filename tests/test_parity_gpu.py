@@ -402,7 +402,8 @@ def test_backward_16bit(dev, kind):
 
 def test_gradient_vs_finite_differences_and_trig(dev):
     """Central differences of the FP64 oracle (h = 1e-3) at 10^4 points away
-    from the piece boundaries; and the distance to the exact-trig gradient."""
+    from the piece boundaries and the folds; and the distance to the
+    exact-trig gradient."""
     rng = np.random.default_rng(51)
     x = (rng.standard_normal(40000) * 3.0).astype(np.float32)
     h = 1e-3
@@ -410,7 +411,9 @@ def test_gradient_vs_finite_differences_and_trig(dev):
     rho, v, _, _, _ = oracle.fold(x64)
     nodes = np.arange(1, 6) * (math.pi / 12)
     dist = np.abs(rho[:, None] - nodes[None, :]).min(axis=1)
-    keep = (dist > 2 * h) & (v > 2 * h)
+    # the fold makes the approximation C^1 but not C^2 at rho = 0 and
+    # rho = pi/2 (D's slope in x flips sign with |r|): keep 2h away too
+    keep = (dist > 2 * h) & (v > 2 * h) & (rho > 2 * h)
     x = x[keep][:10000]
     x64 = x.astype(np.float64)
     say(f"finite differences n={x.size}")
@@ -486,7 +489,7 @@ def test_fused_fwdbwd_full_size(dev):
     ys, gxs = host(y[idx]), host(gx[idx])
     ref_f = oracle.forward(xs.astype(np.float64))
     near, alt = neighbour_values(xs.astype(np.float64))
-    check_f32("fwdbwd-y", xs, ys, ref_f["sin"], alt, near)
+    check_f32("fwdbwd-y:sin", xs, ys, ref_f["sin"], alt, near)
     rg = oracle.grad(xs.astype(np.float64))
     _check_grad("fwdbwd-gx", xs, gs, gxs, rg["sin"],
                 np.abs(gs.astype(np.float64) * rg["sin"]))
