@@ -90,7 +90,15 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="only the headline kernel (for profiling runs)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--profile", action="store_true",
+                    help="run the profiled kernels only (for rocprofv3)")
+    ap.add_argument("--summarize", nargs="+", metavar="ARG",
+                    help="summarize rocprofv3 output: 'trace DIR OUT CMD' or "
+                         "'pmc FETCH_DIR WRITE_DIR OUT CMD'")
     args = ap.parse_args()
+    if args.summarize:
+        summarize(args.summarize)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the map has no cross-GPU step and "
               "this build runs on a single MI355X (use --gpus 1).",
@@ -110,6 +118,9 @@ def main():
     x_host = wl.throughput_mix(n)
     x = torch.from_numpy(x_host).to(dev)
     ys, yc, yt = (torch.empty_like(x) for _ in range(3))
+    if args.profile:
+        profile_pass(args, torch, ta, dev, x, ys, yc, yt)
+        return
 
     def step():
         ta.ta_sincos(x, ys, yc, yt)
@@ -291,6 +302,140 @@ def extras(args, torch, ta, dev):
     res["workload"] = ("ta_sin_fwdbwd, [128, 8192, 512] FP32, x ~ N(0, 100), "
                        "g ~ N(0, 1)")
     return res
+
+
+# ---------------------------------------------------------------------------
+# profiling support: a fixed set of dispatches for rocprofv3, and the
+# summaries committed under profiles/
+# ---------------------------------------------------------------------------
+
+PROFILE_STEPS = 5
+CALIB_BYTES = 1 << 30  # copy 1 in -> 1 out of 2^28 FP32: 1 GiB each way
+
+
+def profile_pass(args, torch, ta, dev, x, ys, yc, yt):
+    """Dispatches, in order: PROFILE_STEPS x ta_sincos (sin+cos+tan, 2^28
+    FP32); PROFILE_STEPS x copy 1 in -> 1 out (2^28 FP32, the counter
+    calibration); PROFILE_STEPS x ta_sin_fwdbwd ([128, 8192, 512] FP32)."""
+    for _ in range(PROFILE_STEPS):
+        ta.ta_sincos(x, ys, yc, yt)
+    torch.cuda.synchronize()
+    log("profiled ta_sincos")
+    for _ in range(PROFILE_STEPS):
+        ta.ta_copy([x], [ys])
+    torch.cuda.synchronize()
+    log("profiled copy 1->1")
+    n2 = 128 * 8192 * 512
+    gen = torch.Generator(device=dev).manual_seed(2024873)
+    x2 = torch.randn(n2, device=dev, generator=gen) * 10.0
+    g2 = torch.randn(n2, device=dev, generator=gen)
+    y2, gx2 = torch.empty_like(x2), torch.empty_like(x2)
+    for _ in range(PROFILE_STEPS):
+        ta.ta_sin_fwdbwd(x2, g2, y2, gx2)
+    torch.cuda.synchronize()
+    log("profiled ta_sin_fwdbwd")
+    print(json.dumps({"profile_pass": "done", "source_sha": source_hash()}))
+
+
+KERNELS = {
+    "sincos_tan_f32": "FwdOp<7, false>",
+    "copy_1to1_f32": "CopyOp<1, 1>",
+    "sin_fwdbwd_f32": "BwdOp<1, true>",
+}
+
+
+def _csv_rows(directory, suffix):
+    import csv
+    import glob
+    rows = []
+    for path in glob.glob(os.path.join(directory, "**", f"*{suffix}"),
+                          recursive=True):
+        with open(path, newline="") as f:
+            rows.extend(csv.DictReader(f))
+    return rows
+
+
+def _which(name):
+    for key, pat in KERNELS.items():
+        if pat in name and "F32" in name:
+            return key
+    return None
+
+
+def summarize(a):
+    mode = a[0]
+    if mode == "trace":
+        directory, out, cmd = a[1], a[2], " ".join(a[3:])
+        rows = _csv_rows(directory, "kernel_stats.csv")
+        lines = [f"# rocprofv3 kernel statistics (kernel-trace --stats)",
+                 f"# command: {cmd}", f"source_sha: {source_hash()}"]
+        for r in rows:
+            key = _which(r.get("Name", ""))
+            if key is None:
+                continue
+            avg_ns = float(r["AverageNs"])
+            lines.append(f"{key}: calls {r['Calls']} average_ns {avg_ns:.0f} "
+                         f"min_ns {float(r['MinNs']):.0f} "
+                         f"max_ns {float(r['MaxNs']):.0f}")
+            if key == "sincos_tan_f32":
+                lines.append(f"sincos_tan_f32_algorithmic_GBs: "
+                             f"{16 * (1 << 28) / avg_ns:.1f}")
+            if key == "sin_fwdbwd_f32":
+                lines.append(f"sin_fwdbwd_f32_algorithmic_GBs: "
+                             f"{16 * 128 * 8192 * 512 / avg_ns:.1f}")
+        _write(out, lines)
+    elif mode == "pmc":
+        fetch_dir, write_dir, out, cmd = a[1], a[2], a[3], " ".join(a[4:])
+        per = {}
+        for counter, directory in (("FETCH_SIZE", fetch_dir),
+                                   ("WRITE_SIZE", write_dir)):
+            for r in _csv_rows(directory, "counter_collection.csv"):
+                if r.get("Counter_Name") != counter:
+                    continue
+                key = _which(r.get("Kernel_Name", ""))
+                if key is None:
+                    continue
+                d = per.setdefault((key, counter), {})
+                disp = r.get("Dispatch_Id") or r.get("Correlation_Id")
+                d[disp] = d.get(disp, 0.0) + float(r["Counter_Value"])
+        lines = [f"# rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE (KiB per dispatch)",
+                 f"# command: {cmd}", f"source_sha: {source_hash()}"]
+        avg = {}
+        for (key, counter), d in sorted(per.items()):
+            v = sum(d.values()) / len(d)
+            avg[(key, counter)] = v
+            lines.append(f"{key}_{counter}_KiB_per_dispatch: {v:.1f} "
+                         f"(dispatches {len(d)})")
+        cf = avg.get(("copy_1to1_f32", "FETCH_SIZE"))
+        cw = avg.get(("copy_1to1_f32", "WRITE_SIZE"))
+        if cf and cw:
+            fs, ws = CALIB_BYTES / (cf * 1024), CALIB_BYTES / (cw * 1024)
+            lines.append(f"calibration: copy 1 in -> 1 out, 2^28 FP32, "
+                         f"{CALIB_BYTES} bytes each way")
+            lines.append(f"fetch_scale: {fs:.4f}")
+            lines.append(f"write_scale: {ws:.4f}")
+            for key, alg in (("sincos_tan_f32", 16 * (1 << 28)),
+                             ("sin_fwdbwd_f32", 16 * 128 * 8192 * 512)):
+                f_ = avg.get((key, "FETCH_SIZE"))
+                w_ = avg.get((key, "WRITE_SIZE"))
+                if f_ is None or w_ is None:
+                    continue
+                hbm = (f_ * fs + w_ * ws) * 1024
+                lines.append(f"{key}_hbm_bytes_per_launch: {hbm:.0f}")
+                lines.append(f"{key}_algorithmic_bytes_per_launch: {alg}")
+                lines.append(f"{key}_traffic_over_algorithmic: {hbm / alg:.4f}")
+                if key == "sincos_tan_f32":
+                    lines.append(f"hbm_bytes_per_launch: {hbm:.0f}")
+        _write(out, lines)
+    else:
+        raise SystemExit(f"unknown summarize mode {mode}")
+
+
+def _write(out, lines):
+    os.makedirs(os.path.dirname(os.path.abspath(out)), exist_ok=True)
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
 
 
 if __name__ == "__main__":

@@ -7,6 +7,7 @@
 // per-piece coefficients live in LDS (one 200-byte copy per workgroup),
 // never in HBM.
 #include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
 #include <stdint.h>
 #include <string.h>
@@ -25,6 +26,7 @@ struct F32 {
   static __device__ float load(raw v) { return __uint_as_float(v); }
   static __device__ raw store(float f) { return __float_as_uint(f); }
 };
+// 16-bit formats also round pairs with one v_cvt_pk_{f16,bf16}_f32.
 struct F16 {
   using raw = uint16_t;
   static __device__ float load(raw v) {
@@ -33,14 +35,21 @@ struct F16 {
   static __device__ raw store(float f) {
     return __half_as_ushort(__float2half_rn(f));
   }
+  static __device__ uint32_t store2(float lo, float hi) {
+    const __half2 h = __float22half2_rn(make_float2(lo, hi));
+    return *reinterpret_cast<const uint32_t *>(&h);
+  }
 };
 struct BF16 {
   using raw = uint16_t;
   static __device__ float load(raw v) { return __uint_as_float(uint32_t(v) << 16); }
   static __device__ raw store(float f) {
-    const uint32_t u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return raw((u >> 16) | 0x40u);  // NaN
-    return raw((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+    const __hip_bfloat16 b = __float2bfloat16(f);
+    return *reinterpret_cast<const raw *>(&b);
+  }
+  static __device__ uint32_t store2(float lo, float hi) {
+    const __hip_bfloat162 b = __float22bfloat162_rn(make_float2(lo, hi));
+    return *reinterpret_cast<const uint32_t *>(&b);
   }
 };
 
@@ -61,11 +70,11 @@ struct FwdOp {
     int o = 0;
     if constexpr ((MASK & (kSin | kCos)) != 0) {
       const float y = rsqrt_refined(v.q);
-      if constexpr (MASK & kSin) out[o++] = with_sign(v.n * y, sin_sign(f));
-      if constexpr (MASK & kCos) out[o++] = with_sign(v.d * y, cos_sign(f));
+      if constexpr (MASK & kSin) out[o++] = set_sign(v.n * y, sin_mask(f));
+      if constexpr (MASK & kCos) out[o++] = set_sign(v.d * y, cos_mask(f));
     }
     if constexpr (MASK & kTan) {
-      float t = with_sign(div_refined(v.n, v.d), tan_sign(f));
+      float t = set_sign(div_refined(v.n, v.d), tan_mask(f));
       if constexpr (GUARD) {
         // Section 3 proposed_tan: +inf within 1e-3 of pi/2, before the sign.
         if ((f.q & 1u) && f.a < 1e-3) t = __builtin_inff();
@@ -84,11 +93,11 @@ struct TaylorOp {
     const Folded f = fold(in[0]);
     const float rho = fold_rho(f);
     if constexpr (MASK == kSin)
-      out[0] = with_sign(taylor_sin_unsigned<TERMS>(rho), sin_sign(f));
+      out[0] = flip_sign(taylor_sin_unsigned<TERMS>(rho), sin_mask(f));
     if constexpr (MASK == kCos)
-      out[0] = with_sign(taylor_cos_unsigned<TERMS>(rho), cos_sign(f));
+      out[0] = flip_sign(taylor_cos_unsigned<TERMS>(rho), cos_mask(f));
     if constexpr (MASK == kTan)
-      out[0] = with_sign(taylor_tan_unsigned<TERMS>(rho), tan_sign(f));
+      out[0] = flip_sign(taylor_tan_unsigned<TERMS>(rho), tan_mask(f));
   }
 };
 
@@ -104,16 +113,16 @@ struct BwdOp {
   __device__ static void apply(const float *in, float *out, const Tables &tb) {
     const Folded f = fold(in[0]);
     const Forms v = forms(f, tb);
-    const float kdet = tb.kdet[f.idx];
+    const float kdet = tb.kdet[f.row];
     if constexpr (WHICH == kTan) {
       const float r = rcp_refined(v.d);
       const float dt = kdet * r * r;
-      if constexpr (WITH_Y) out[0] = with_sign(div_refined(v.n, v.d), tan_sign(f));
+      if constexpr (WITH_Y) out[0] = set_sign(div_refined(v.n, v.d), tan_mask(f));
       out[WITH_Y ? 1 : 0] = in[1] * dt;
     } else {
       const float y = rsqrt_refined(v.q);
-      const float s = with_sign(v.n * y, sin_sign(f));
-      const float c = with_sign(v.d * y, cos_sign(f));
+      const float s = set_sign(v.n * y, sin_mask(f));
+      const float c = set_sign(v.d * y, cos_mask(f));
       const float omega = kdet * y * y;
       if constexpr (WHICH == kSin) {
         if constexpr (WITH_Y) out[0] = s;
@@ -136,11 +145,11 @@ struct SinCosBwdOp {
     const Folded f = fold(in[0]);
     const Forms v = forms(f, tb);
     const float y = rsqrt_refined(v.q);
-    const float omega = tb.kdet[f.idx] * y * y;
+    const float omega = tb.kdet[f.row] * y * y;
     float acc = 0.0f;
-    if constexpr (HAS_GS) acc = in[1] * with_sign(v.d * y, cos_sign(f));
+    if constexpr (HAS_GS) acc = in[1] * set_sign(v.d * y, cos_mask(f));
     if constexpr (HAS_GC)
-      acc = __builtin_fmaf(-in[HAS_GS ? 2 : 1], with_sign(v.n * y, sin_sign(f)),
+      acc = __builtin_fmaf(-in[HAS_GS ? 2 : 1], set_sign(v.n * y, sin_mask(f)),
                            acc);
     out[0] = omega * acc;
   }
@@ -293,7 +302,7 @@ __global__ __launch_bounds__(BLOCK) void map_vec_kernel(IoPtrs io, int64_t head,
   for (int u = 0; u < UNROLL; ++u) {
     const int64_t v = v0 + int64_t(u) * BLOCK;
     if (v < nvec) {
-      u32x4 out_raw[Op::NOUT];
+      float res[Op::NOUT][VEC];
 #pragma unroll
       for (int e = 0; e < VEC; ++e) {
         float in[Op::NIN], out[Op::NOUT];
@@ -302,11 +311,20 @@ __global__ __launch_bounds__(BLOCK) void map_vec_kernel(IoPtrs io, int64_t head,
           in[k] = ST::load(reinterpret_cast<const raw *>(&in_raw[u][k])[e]);
         Op::apply(in, out, tb);
 #pragma unroll
-        for (int k = 0; k < Op::NOUT; ++k)
-          reinterpret_cast<raw *>(&out_raw[k])[e] = ST::store(out[k]);
+        for (int k = 0; k < Op::NOUT; ++k) res[k][e] = out[k];
       }
 #pragma unroll
-      for (int k = 0; k < Op::NOUT; ++k) vstore<NTS>(out_base[k], v, out_raw[k]);
+      for (int k = 0; k < Op::NOUT; ++k) {
+        u32x4 w;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          if constexpr (VEC == 4)
+            w[j] = ST::store(res[k][j]);
+          else
+            w[j] = ST::store2(res[k][2 * j], res[k][2 * j + 1]);
+        }
+        vstore<NTS>(out_base[k], v, w);
+      }
     }
   }
   if (blockIdx.x == 0) {

@@ -49,7 +49,8 @@ constexpr int kB[6] = {0, 10, 46, 217, 297, 542};
 constexpr int kC[6] = {-1, -4, -5, -13, -10, -11};
 constexpr int kD[6] = {632, 657, 541, 1252, 910, 990};
 
-// Row `idx` = j + 3*(q & 1) of the per-element coefficient table, where j is
+// Logical row idx = j + 3*(q & 1) of the per-element coefficient table (kept
+// in LDS slot j + 4*(q & 1)), where j is
 // the 15-degree slot of a = |r| in [0, 45] degrees.  q even: rho = a, piece
 // k = j, N = b + a_k t, D = d + c_k t.  q odd: rho = 90 - a, piece k = 5 - j,
 // and with t = a (the complement) N = (90 a_k + b_k) - a_k t and
@@ -77,10 +78,11 @@ __host__ __device__ constexpr double kdet_of_row(int idx) {
   return kDegPerRad * double(kA[k] * kD[k] - kB[k] * kC[k]);
 }
 
-// Per-workgroup copy of the table in LDS (no table in HBM).
+// Per-workgroup copy of the table in LDS (no table in HBM).  Rows are
+// indexed j + 4*(q & 1): rows 0-2 even quadrants, 4-6 odd, 3 and 7 unused.
 struct Tables {
-  PieceRow row[6];
-  float kdet[6];
+  PieceRow row[8];
+  float kdet[8];
 };
 
 // One lane writes the table with immediates; the caller synchronises.
@@ -88,9 +90,12 @@ __device__ inline void init_tables(Tables &tb) {
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
-      tb.row[i] = piece_row(i);
-      tb.kdet[i] = float(kdet_of_row(i));
+      const int slot = i < 3 ? i : i + 1;
+      tb.row[slot] = piece_row(i);
+      tb.kdet[slot] = float(kdet_of_row(i));
     }
+    tb.row[3] = tb.row[7] = PieceRow{0.0, 0.0, 1.0, 0.0};
+    tb.kdet[3] = tb.kdet[7] = 0.0f;
   }
 }
 
@@ -160,11 +165,11 @@ __device__ inline void reduce(float x, double &r, uint32_t &q) {
 
 // Folded element: everything the later stages need.
 struct Folded {
-  double t;      // |r| in degrees, [0, 45]
-  double a;      // |r| in radians
-  uint32_t q;    // quadrant, low bits
-  uint32_t sr;   // sign bit of r
-  int idx;       // table row j + 3*(q & 1)
+  double t;       // |r| in degrees, [0, 45]
+  double a;       // |r| in radians
+  uint32_t q;     // quadrant, low bits
+  uint32_t hr;    // high word of r: bit 31 = sign of r
+  uint32_t row;   // LDS table slot j + 4*(q & 1)
 };
 
 __device__ inline Folded fold(float x) {
@@ -172,27 +177,38 @@ __device__ inline Folded fold(float x) {
   uint32_t q;
   reduce(x, r, q);
   Folded f;
-  f.sr = uint32_t(__double2hiint(r)) >> 31;
+  f.hr = uint32_t(__double2hiint(r));
   f.a = __builtin_fabs(r);
   f.t = f.a * kDegPerRad;
-  const int j = int(f.t >= 15.0) + int(f.t >= 30.0);
+  // j = 15-degree slot of |r|; the family (q & 1) selects slots 4..6
+  const uint32_t j = f.t >= 30.0 ? 2u : (f.t >= 15.0 ? 1u : 0u);
   f.q = q;
-  f.idx = j + 3 * int(q & 1u);
+  f.row = ((q << 2) & 4u) | j;
   return f;
 }
 
-// Sign bits (1 = negative) of sin, cos, tan for quadrant q and sign of r.
-__device__ inline uint32_t sin_sign(const Folded &f) {
-  return ((f.q & 1u) ? 0u : f.sr) ^ ((f.q >> 1) & 1u);
+// Output signs as bit 31 of a word (other bits are don't-care), from the
+// quadrant q and the sign of r, sr:
+//   sin: sr ^ q1 for even q, q1 for odd q;
+//   cos: q0 ^ q1 for even q, q0 ^ q1 ^ sr for odd q;
+//   tan: sr ^ q0.
+__device__ inline uint32_t odd_mask(const Folded &f) { return 0u - (f.q & 1u); }
+__device__ inline uint32_t sin_mask(const Folded &f) {
+  return (f.hr & ~odd_mask(f)) ^ (f.q << 30);
 }
-__device__ inline uint32_t cos_sign(const Folded &f) {
-  return ((f.q ^ (f.q >> 1)) & 1u) ^ ((f.q & 1u) ? f.sr : 0u);
+__device__ inline uint32_t cos_mask(const Folded &f) {
+  return (f.hr & odd_mask(f)) ^ (f.q << 30) ^ (f.q << 31);
 }
-__device__ inline uint32_t tan_sign(const Folded &f) {
-  return f.sr ^ (f.q & 1u);
+__device__ inline uint32_t tan_mask(const Folded &f) { return f.hr ^ (f.q << 31); }
+
+// Sets the sign of a non-negative value v to bit 31 of m (one v_bfi_b32).
+__device__ inline float set_sign(float v, uint32_t m) {
+  return __uint_as_float((__float_as_uint(v) & 0x7fffffffu) |
+                         (m & 0x80000000u));
 }
-__device__ inline float with_sign(float v, uint32_t neg) {
-  return __uint_as_float(__float_as_uint(v) ^ (neg << 31));
+// Flips the sign of v by bit 31 of m.
+__device__ inline float flip_sign(float v, uint32_t m) {
+  return __uint_as_float(__float_as_uint(v) ^ (m & 0x80000000u));
 }
 
 // ---------------------------------------------------------------------------
@@ -203,7 +219,7 @@ struct Forms {
 };
 
 __device__ inline Forms forms(const Folded &f, const Tables &tb) {
-  const PieceRow c = tb.row[f.idx];
+  const PieceRow c = tb.row[f.row];
   const double nd = __builtin_fma(c.sN, f.t, c.iN);
   const double dd = __builtin_fma(c.sD, f.t, c.iD);
   const double qd = __builtin_fma(nd, nd, dd * dd);
