@@ -85,8 +85,8 @@ def pmc_traffic():
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-extras", action="store_true",
                     help="only the headline kernel (for profiling runs)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
@@ -314,9 +314,10 @@ CALIB_BYTES = 1 << 30  # copy 1 in -> 1 out of 2^28 FP32: 1 GiB each way
 
 
 def profile_pass(args, torch, ta, dev, x, ys, yc, yt):
-    """Dispatches, in order: PROFILE_STEPS x ta_sincos (sin+cos+tan, 2^28
-    FP32); PROFILE_STEPS x copy 1 in -> 1 out (2^28 FP32, the counter
-    calibration); PROFILE_STEPS x ta_sin_fwdbwd ([128, 8192, 512] FP32)."""
+    """Dispatches, in order, PROFILE_STEPS of each: ta_sincos (sin+cos+tan,
+    2^28 FP32); copy 1 in -> 1 out (2^28 FP32, the counter calibration);
+    ta_sin_fwdbwd ([128, 8192, 512] FP32); ta_sin (2^28 FP32); ta_sincos
+    and ta_sin on 2^29 BF16 U[-pi, pi]."""
     for _ in range(PROFILE_STEPS):
         ta.ta_sincos(x, ys, yc, yt)
     torch.cuda.synchronize()
@@ -334,14 +335,35 @@ def profile_pass(args, torch, ta, dev, x, ys, yc, yt):
         ta.ta_sin_fwdbwd(x2, g2, y2, gx2)
     torch.cuda.synchronize()
     log("profiled ta_sin_fwdbwd")
+    del x2, g2, y2, gx2
+    for _ in range(PROFILE_STEPS):
+        ta.ta_sin(x, ys)
+    torch.cuda.synchronize()
+    log("profiled ta_sin")
+    xb = (torch.rand(1 << 29, device=dev, generator=gen, dtype=torch.float64)
+          * (2 * math.pi) - math.pi).to(torch.bfloat16)
+    bs, bc, bt = (torch.empty_like(xb) for _ in range(3))
+    for _ in range(PROFILE_STEPS):
+        ta.ta_sincos(xb, bs, bc, bt)
+    for _ in range(PROFILE_STEPS):
+        ta.ta_sin(xb, bs)
+    torch.cuda.synchronize()
+    log("profiled BF16 ta_sincos / ta_sin")
     print(json.dumps({"profile_pass": "done", "source_sha": source_hash()}))
 
 
 KERNELS = {
-    "sincos_tan_f32": "FwdOp<7, false>",
-    "copy_1to1_f32": "CopyOp<1, 1>",
-    "sin_fwdbwd_f32": "BwdOp<1, true>",
+    "sincos_tan_f32": ("F32", "FwdOp<7, false>"),
+    "copy_1to1_f32": ("F32", "CopyOp<1, 1>"),
+    "sin_fwdbwd_f32": ("F32", "BwdOp<1, true>"),
+    "sin_f32": ("F32", "FwdOp<1, false>"),
+    "sincos_tan_bf16": ("BF16", "FwdOp<7, false>"),
+    "sin_bf16": ("BF16", "FwdOp<1, false>"),
 }
+ELEMS = {"sincos_tan_f32": 1 << 28, "copy_1to1_f32": 1 << 28,
+         "sin_fwdbwd_f32": 128 * 8192 * 512, "sin_f32": 1 << 28,
+         "sincos_tan_bf16": 1 << 29, "sin_bf16": 1 << 29}
+VALU_PEAK = 256 * 4 * 16 * 2.4e9  # lane-instructions/s (VALU issue)
 
 
 def _csv_rows(directory, suffix):
@@ -356,8 +378,8 @@ def _csv_rows(directory, suffix):
 
 
 def _which(name):
-    for key, pat in KERNELS.items():
-        if pat in name and "F32" in name:
+    for key, (st, pat) in KERNELS.items():
+        if pat in name and f"ta::{st}," in name:
             return key
     return None
 
@@ -426,6 +448,28 @@ def summarize(a):
                 lines.append(f"{key}_traffic_over_algorithmic: {hbm / alg:.4f}")
                 if key == "sincos_tan_f32":
                     lines.append(f"hbm_bytes_per_launch: {hbm:.0f}")
+        _write(out, lines)
+    elif mode == "sq":
+        directory, out, cmd = a[1], a[2], " ".join(a[3:])
+        per = {}
+        for r in _csv_rows(directory, "counter_collection.csv"):
+            key = _which(r.get("Kernel_Name", ""))
+            if key is None:
+                continue
+            d = per.setdefault(key, {}).setdefault(r["Counter_Name"], {})
+            disp = r.get("Dispatch_Id") or r.get("Correlation_Id")
+            d[disp] = d.get(disp, 0.0) + float(r["Counter_Value"])
+        lines = ["# rocprofv3 --pmc SQ instruction counters (per dispatch)",
+                 f"# command: {cmd}", f"source_sha: {source_hash()}",
+                 "# per_elem = wave instructions * 64 lanes / elements"]
+        for key, counters in sorted(per.items()):
+            n = ELEMS[key]
+            for cname, d in sorted(counters.items()):
+                v = sum(d.values()) / len(d)
+                extra = ""
+                if cname.startswith("SQ_INSTS"):
+                    extra = f" per_elem {v * 64 / n:.2f}"
+                lines.append(f"{key}_{cname}: {v:.0f}{extra}")
         _write(out, lines)
     else:
         raise SystemExit(f"unknown summarize mode {mode}")
