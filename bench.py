@@ -233,6 +233,15 @@ def comparators(x, x_host, n, args, torch, ta, np):
                       "error_vs_libm": errors({"sin": ys, "cos": yc,
                                                "tan": yt})}
 
+    def fp():
+        ta.ta_paper_sincos(x, ys, yc, yt, 0)
+    log("timing ta_paper_sincos (the paper's literal FISR arithmetic)")
+    per, total, _ = time_launches(fp, args.steps, args.warmup, torch)
+    ms = total / args.steps
+    res["ta_paper_sincos_fisr_fp64"] = {
+        "gelem_s": round(n / (ms * 1e-3) / 1e9, 2), "ms": round(ms, 5),
+        "error_vs_libm": errors({"sin": ys, "cos": yc, "tan": yt})}
+
     def f2():
         ta.ta_sincos(x, ys, yc, None)
     per, total, _ = time_launches(f2, args.steps, args.warmup, torch)

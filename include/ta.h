@@ -61,7 +61,11 @@ enum {
   /* The pseudocode of proposed_tan (Section 3) returns +infinity, before the
    * sign is applied, when the folded angle is within 1e-3 of pi/2.  Off by
    * default (the formula is then used all the way to the pole). */
-  TA_FLAG_TAN_GUARD = 1u
+  TA_FLAG_TAN_GUARD = 1u,
+  /* ta_paper_sincos only: index the pieces by floor(rho / 0.261) as the
+   * pseudocode of proposed_sin / proposed_tan does (clamped to the last
+   * piece) instead of the pi/12 intervals of Section 2. */
+  TA_FLAG_LITERAL_DIVISOR = 2u
 };
 
 /* ---- forward: the proposed functions (Section 2 formulas, Section 3 fold) */
@@ -123,6 +127,20 @@ ta_status ta_cos_fwdbwd(const void *x, const void *gy, void *y, void *gx,
                         int64_t n, ta_dtype dt, hipStream_t stream);
 ta_status ta_tan_fwdbwd(const void *x, const void *gy, void *y, void *gx,
                         int64_t n, ta_dtype dt, hipStream_t stream);
+
+/* ---- the paper's literal arithmetic (Section 3, Algorithms 1-4) ---------
+ * Same fold and signs, then in FP64: radian coefficients a_k*180/pi,
+ * c_k*180/pi (b_k, d_k unchanged), piece index floor(rho / (pi/12)),
+ * sin = (a rho + b) * FISR(x rho^2 + y rho + z), cos likewise with
+ * (c rho + d), tan = (a rho + b) * FISR(c rho + d)^2, where FISR is
+ * Algorithm 1 (magic constant 0x5fe6eb50c7b537a9, one Newton step).  Results
+ * are rounded to the storage dtype.  This reproduces the error statistics of
+ * Tables 1-3 (maximum sin/cos error 1.532e-3); it is ~3x less accurate than
+ * ta_sincos.  Any non-empty subset of ys/yc/yt; flags: TA_FLAG_TAN_GUARD,
+ * TA_FLAG_LITERAL_DIVISOR. */
+ta_status ta_paper_sincos(const void *x, void *ys, void *yc, void *yt,
+                          int64_t n, ta_dtype dt, uint32_t flags,
+                          hipStream_t stream);
 
 /* ---- measurement comparators (not part of the method) -------------------
  * The same load/store skeleton around the GPU's built-in functions:

@@ -54,6 +54,8 @@ def _load():
     lib.ta_or_taylor_map.argtypes = [D, i64, ctypes.c_int, D, D, D, D, D, D]
     lib.ta_or_grad_map.argtypes = [D, i64, D, D, D]
     lib.ta_or_fisr_map.argtypes = [D, i64, ctypes.c_double, D, D, D]
+    lib.ta_or_paper_map.argtypes = [D, i64, ctypes.c_double, ctypes.c_uint,
+                                    D, D, D]
     lib.ta_or_piece.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                 D, D]
     lib.ta_or_piece_scs.argtypes = [ctypes.c_int, ctypes.c_double,
@@ -168,4 +170,16 @@ def fisr(rho, divisor: float = np.pi / 12):
     out = {k: np.empty(n) for k in ("sin", "cos", "tan")}
     lib.ta_or_fisr_map(_dp(rho), n, float(divisor), _dp(out["sin"]),
                        _dp(out["cos"]), _dp(out["tan"]))
+    return out
+
+
+def paper(x, divisor: float = np.pi / 12, flags: int = 0):
+    """The paper's literal arithmetic (fold, Algorithms 1-4, guard) on
+    angles x; signed outputs."""
+    lib = _load()
+    x = _x(x)
+    n = x.size
+    out = {k: np.empty(n) for k in ("sin", "cos", "tan")}
+    lib.ta_or_paper_map(_dp(x), n, float(divisor), int(flags),
+                        _dp(out["sin"]), _dp(out["cos"]), _dp(out["tan"]))
     return out

@@ -326,24 +326,62 @@ static double or_fisr(double number) {
   return y;
 }
 
+/* Algorithms 2-4 on one folded angle `ang` in [0, pi/2]: piece index
+ * floor(ang/divisor) (clamped to the last piece), radian coefficients
+ * a = a_k*K, c = c_k*K with b, d unchanged, the quadratic x ang^2 + y ang + z
+ * with x = a^2 + c^2, y = 2(ab + cd), z = b^2 + d^2 (Appendix A.4), and the
+ * fast inverse square root in place of 1/sqrt and of the division. */
+static void or_fisr_eval(double ang, double divisor, double *ys, double *yc,
+                         double *yt) {
+  double K = or_k();
+  int k = (int)floor(ang / divisor);
+  if (k > 5) k = 5;
+  if (k < 0) k = 0;
+  double a = OR_A[k] * K, b = OR_B[k], c = OR_C[k] * K, d = OR_D[k];
+  double qx = a * a + c * c, qy = 2.0 * (a * b + c * d), qz = b * b + d * d;
+  double poly_s = a * ang + b;          /* Algorithm 2: poly */
+  double ang2 = ang * ang;              /* Algorithm 2: ang2 */
+  double inner = qx * ang2 + qy * ang + qz;
+  double inv = or_fisr(inner);
+  *ys = poly_s * inv;
+  double poly_c = c * ang + d;          /* Algorithm 3 */
+  *yc = poly_c * inv;
+  double tmp = or_fisr(c * ang + d);    /* Algorithm 4 */
+  *yt = poly_s * (tmp * tmp);
+}
+
 void ta_or_fisr_map(const double *rho, int64_t n, double divisor, double *ys,
                     double *yc, double *yt) {
-  double K = or_k();
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; ++i) {
-    double ang = rho[i];
-    int k = (int)floor(ang / divisor);
-    if (k > 5) k = 5;
-    if (k < 0) k = 0;
-    double a = OR_A[k] * K, b = OR_B[k], c = OR_C[k] * K, d = OR_D[k];
-    double qx = a * a + c * c, qy = 2.0 * (a * b + c * d), qz = b * b + d * d;
-    double inner = qx * ang * ang + qy * ang + qz; /* Algorithm 2 */
-    double inv = or_fisr(inner);
-    if (ys) ys[i] = (a * ang + b) * inv;
-    if (yc) yc[i] = (c * ang + d) * inv; /* Algorithm 3 */
-    if (yt) {
-      double tmp = or_fisr(c * ang + d); /* Algorithm 4 */
-      yt[i] = (a * ang + b) * (tmp * tmp);
+    double s, c, t;
+    or_fisr_eval(rho[i], divisor, &s, &c, &t);
+    if (ys) ys[i] = s;
+    if (yc) yc[i] = c;
+    if (yt) yt[i] = t;
+  }
+}
+
+/* The paper's arithmetic on angles x: the Section 3 fold and signs around
+ * or_fisr_eval, and proposed_tan's guard (+inf, unsigned, when the folded
+ * angle is within 1e-3 of pi/2) when TA_OR_TAN_GUARD is set. */
+void ta_or_paper_map(const double *x, int64_t n, double divisor,
+                     unsigned flags, double *ys, double *yc, double *yt) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    double s = NAN, c = NAN, t = NAN;
+    if (!(isnan(x[i]) || isinf(x[i]))) {
+      double rho, v;
+      int ns, nc;
+      ta_or_fold(x[i], &rho, &v, &ns, &nc);
+      or_fisr_eval(rho, divisor, &s, &c, &t);
+      s = ns ? -s : s;
+      c = nc ? -c : c;
+      t = (ns != nc) ? -t : t;
+      if ((flags & TA_OR_TAN_GUARD) && v < 1e-3) t = INFINITY;
     }
+    if (ys) ys[i] = s;
+    if (yc) yc[i] = c;
+    if (yt) yt[i] = t;
   }
 }

@@ -27,10 +27,10 @@ __all__ = [
     "ta_taylor_sin", "ta_taylor_cos", "ta_taylor_tan",
     "ta_sin_bwd", "ta_cos_bwd", "ta_tan_bwd", "ta_sincos_bwd",
     "ta_sin_fwdbwd", "ta_cos_fwdbwd", "ta_tan_fwdbwd",
-    "ta_builtin_sincos", "ta_copy",
+    "ta_paper_sincos", "ta_builtin_sincos", "ta_copy",
     "sin", "cos", "tan", "sincos", "taylor",
     "SinFn", "CosFn", "TanFn", "SinCosFn",
-    "TA_FLAG_TAN_GUARD",
+    "TA_FLAG_TAN_GUARD", "TA_FLAG_LITERAL_DIVISOR", "paper_sincos",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -38,6 +38,7 @@ _LIB = os.path.join(_HERE, "libta.so")
 
 TA_F32, TA_F16, TA_BF16 = 0, 1, 2
 TA_FLAG_TAN_GUARD = 1
+TA_FLAG_LITERAL_DIVISOR = 2
 _DTYPE_CODE = {torch.float32: TA_F32, torch.float16: TA_F16,
                torch.bfloat16: TA_BF16}
 
@@ -81,6 +82,7 @@ def load(path: str | None = None):
         "ta_sin_fwdbwd": [vp, vp, vp, vp, i64, i32, vp],
         "ta_cos_fwdbwd": [vp, vp, vp, vp, i64, i32, vp],
         "ta_tan_fwdbwd": [vp, vp, vp, vp, i64, i32, vp],
+        "ta_paper_sincos": [vp, vp, vp, vp, i64, i32, u32, vp],
         "ta_builtin_sincos": [vp, vp, vp, vp, i64, i32, i32, vp],
         "ta_copy": [ctypes.POINTER(vp), i32, ctypes.POINTER(vp), i32, i64,
                     i32, vp],
@@ -238,6 +240,15 @@ ta_cos_fwdbwd = _fwdbwd_entry("ta_cos_fwdbwd")
 ta_tan_fwdbwd = _fwdbwd_entry("ta_tan_fwdbwd")
 
 
+def ta_paper_sincos(x, ys=None, yc=None, yt=None, flags: int = 0):
+    """The paper's literal arithmetic (Algorithms 1-4: FISR in FP64) on the
+    same fold; any non-empty subset of outputs."""
+    _dev(x, "x"); _same(x, ("ys", ys), ("yc", yc), ("yt", yt))
+    n, dt, s = _args(x)
+    _check(load().ta_paper_sincos(_ptr(x), _ptr(ys), _ptr(yc), _ptr(yt), n,
+                                  dt, int(flags), s))
+
+
 def ta_builtin_sincos(x, ys, yc, yt=None, kind: int = 0):
     """Comparator: the GPU's built-in sinf/cosf/tanf (kind 0), __sinf/...
     (kind 1) or sincosf (kind 2) in the same streaming skeleton."""
@@ -287,6 +298,16 @@ def sincos(x, with_tan: bool = False, guard: bool = False):
     yt = torch.empty_like(x) if with_tan else None
     ta_sincos_ex(x, ys, yc, yt, TA_FLAG_TAN_GUARD if guard else 0)
     return (ys, yc, yt) if with_tan else (ys, yc)
+
+
+def paper_sincos(x, guard: bool = False, literal_divisor: bool = False):
+    """(sin, cos, tan) with the paper's literal arithmetic."""
+    x = _c(x)
+    ys, yc, yt = (torch.empty_like(x) for _ in range(3))
+    flags = (TA_FLAG_TAN_GUARD if guard else 0) | \
+        (TA_FLAG_LITERAL_DIVISOR if literal_divisor else 0)
+    ta_paper_sincos(x, ys, yc, yt, flags)
+    return ys, yc, yt
 
 
 def taylor(x, fn: str, terms: int = 5):

@@ -63,8 +63,9 @@ struct FwdOp {
   static constexpr int NIN = 1;
   static constexpr int NOUT = ((MASK & kSin) ? 1 : 0) + ((MASK & kCos) ? 1 : 0) +
                               ((MASK & kTan) ? 1 : 0);
-  static constexpr bool kNeedsTables = true;
-  __device__ static void apply(const float *in, float *out, const Tables &tb) {
+  using Table = Tables;
+  __device__ static void apply(const float *in, float *out, const Table &tb,
+                                  uint32_t) {
     const Folded f = fold(in[0]);
     const Forms v = forms(f, tb);
     int o = 0;
@@ -88,8 +89,9 @@ template <int MASK, int TERMS>
 struct TaylorOp {
   static constexpr int NIN = 1;
   static constexpr int NOUT = 1;
-  static constexpr bool kNeedsTables = false;
-  __device__ static void apply(const float *in, float *out, const Tables &) {
+  using Table = NoTable;
+  __device__ static void apply(const float *in, float *out, const Table &,
+                                  uint32_t) {
     const Folded f = fold(in[0]);
     const float rho = fold_rho(f);
     if constexpr (MASK == kSin)
@@ -109,8 +111,9 @@ template <int WHICH, bool WITH_Y>
 struct BwdOp {
   static constexpr int NIN = 2;  // x, gy
   static constexpr int NOUT = WITH_Y ? 2 : 1;
-  static constexpr bool kNeedsTables = true;
-  __device__ static void apply(const float *in, float *out, const Tables &tb) {
+  using Table = Tables;
+  __device__ static void apply(const float *in, float *out, const Table &tb,
+                                  uint32_t) {
     const Folded f = fold(in[0]);
     const Forms v = forms(f, tb);
     const float kdet = tb.kdet[f.row];
@@ -140,8 +143,9 @@ template <bool HAS_GS, bool HAS_GC>
 struct SinCosBwdOp {
   static constexpr int NIN = 1 + (HAS_GS ? 1 : 0) + (HAS_GC ? 1 : 0);
   static constexpr int NOUT = 1;
-  static constexpr bool kNeedsTables = true;
-  __device__ static void apply(const float *in, float *out, const Tables &tb) {
+  using Table = Tables;
+  __device__ static void apply(const float *in, float *out, const Table &tb,
+                                  uint32_t) {
     const Folded f = fold(in[0]);
     const Forms v = forms(f, tb);
     const float y = rsqrt_refined(v.q);
@@ -155,13 +159,43 @@ struct SinCosBwdOp {
   }
 };
 
+// The paper's literal arithmetic (Algorithms 1-4 in FP64) on the same fold
+// and signs; flags: TA_FLAG_TAN_GUARD, TA_FLAG_LITERAL_DIVISOR.
+template <int MASK>
+struct PaperOp {
+  static constexpr int NIN = 1;
+  static constexpr int NOUT = ((MASK & kSin) ? 1 : 0) + ((MASK & kCos) ? 1 : 0) +
+                              ((MASK & kTan) ? 1 : 0);
+  using Table = PaperTables;
+  __device__ static void apply(const float *in, float *out, const Table &tb,
+                               uint32_t flags) {
+    const Folded f = fold(in[0]);
+    const double ang = (f.q & 1u) ? (kPio2Hi - f.a) + kPio2Lo : f.a;
+    const double divisor =
+        (flags & TA_FLAG_LITERAL_DIVISOR) ? kLiteralDivisor : kPi12;
+    double s, c, t;
+    paper_eval(ang, divisor, tb, s, c, t);
+    int o = 0;
+    if constexpr (MASK & kSin) out[o++] = flip_sign(float(s), sin_mask(f));
+    if constexpr (MASK & kCos) out[o++] = flip_sign(float(c), cos_mask(f));
+    if constexpr (MASK & kTan) {
+      float tt = flip_sign(float(t), tan_mask(f));
+      // proposed_tan: +inf within 1e-3 of pi/2, before the sign
+      if ((flags & TA_FLAG_TAN_GUARD) && (f.q & 1u) && f.a < 1e-3)
+        tt = __builtin_inff();
+      out[o++] = tt;
+    }
+  }
+};
+
 // Comparators: the GPU's built-in functions in the same skeleton.
 template <int KIND, bool WITH_TAN>
 struct BuiltinOp {
   static constexpr int NIN = 1;
   static constexpr int NOUT = WITH_TAN ? 3 : 2;
-  static constexpr bool kNeedsTables = false;
-  __device__ static void apply(const float *in, float *out, const Tables &) {
+  using Table = NoTable;
+  __device__ static void apply(const float *in, float *out, const Table &,
+                                  uint32_t) {
     const float x = in[0];
     if constexpr (KIND == 0) {
       out[0] = sinf(x);
@@ -185,8 +219,9 @@ template <int NI, int NO>
 struct CopyOp {
   static constexpr int NIN = NI;
   static constexpr int NOUT = NO;
-  static constexpr bool kNeedsTables = false;
-  __device__ static void apply(const float *in, float *out, const Tables &) {
+  using Table = NoTable;
+  __device__ static void apply(const float *in, float *out, const Table &,
+                                  uint32_t) {
 #pragma unroll
     for (int j = 0; j < NO; ++j) out[j] = in[j % NI];
   }
@@ -198,6 +233,7 @@ struct CopyOp {
 struct IoPtrs {
   const char *in[3];
   char *out[3];
+  uint32_t flags;  // runtime flag bits for the element functor
 };
 
 template <class ST>
@@ -254,13 +290,13 @@ __device__ inline void vstore(char *base, int64_t v, u32x4 x) {
 
 template <class ST, class Op>
 __device__ inline void scalar_element(const IoPtrs &io, int64_t i,
-                                      const Tables &tb) {
+                                      const typename Op::Table &tb) {
   using raw = typename ST::raw;
   float in[Op::NIN], out[Op::NOUT];
 #pragma unroll
   for (int k = 0; k < Op::NIN; ++k)
     in[k] = ST::load(reinterpret_cast<const raw *>(io.in[k])[i]);
-  Op::apply(in, out, tb);
+  Op::apply(in, out, tb, io.flags);
 #pragma unroll
   for (int k = 0; k < Op::NOUT; ++k)
     reinterpret_cast<raw *>(io.out[k])[i] = ST::store(out[k]);
@@ -275,9 +311,9 @@ __global__ __launch_bounds__(BLOCK) void map_vec_kernel(IoPtrs io, int64_t head,
                                                         int64_t nvec, int64_t n) {
   using raw = typename ST::raw;
   constexpr int VEC = Vec<ST>::kElems;
-  __shared__ Tables tb;
-  if constexpr (Op::kNeedsTables) {
-    init_tables(tb);
+  __shared__ typename Op::Table tb;
+  if constexpr (Op::Table::kUsed) {
+    Op::Table::init(tb);
     __syncthreads();
   }
   const int64_t v0 = int64_t(blockIdx.x) * (UNROLL * BLOCK) + threadIdx.x;
@@ -309,7 +345,7 @@ __global__ __launch_bounds__(BLOCK) void map_vec_kernel(IoPtrs io, int64_t head,
 #pragma unroll
         for (int k = 0; k < Op::NIN; ++k)
           in[k] = ST::load(reinterpret_cast<const raw *>(&in_raw[u][k])[e]);
-        Op::apply(in, out, tb);
+        Op::apply(in, out, tb, io.flags);
 #pragma unroll
         for (int k = 0; k < Op::NOUT; ++k) res[k][e] = out[k];
       }
@@ -340,9 +376,9 @@ constexpr int kScalarBlock = 256;
 template <class ST, class Op>
 __global__ __launch_bounds__(kScalarBlock) void map_scalar_kernel(IoPtrs io,
                                                                   int64_t n) {
-  __shared__ Tables tb;
-  if constexpr (Op::kNeedsTables) {
-    init_tables(tb);
+  __shared__ typename Op::Table tb;
+  if constexpr (Op::Table::kUsed) {
+    Op::Table::init(tb);
     __syncthreads();
   }
   const int64_t stride = int64_t(gridDim.x) * kScalarBlock;
@@ -353,10 +389,11 @@ __global__ __launch_bounds__(kScalarBlock) void map_scalar_kernel(IoPtrs io,
 
 template <class ST, class Op>
 hipError_t launch_map(const void *const *in, void *const *out, int64_t n,
-                      hipStream_t stream) {
+                      hipStream_t stream, uint32_t flags) {
   using raw = typename ST::raw;
   constexpr int VEC = Vec<ST>::kElems;
   IoPtrs io{};
+  io.flags = flags;
   const uintptr_t mis = uintptr_t(in[0]) & 15u;
   bool same = (mis % sizeof(raw)) == 0;
   for (int k = 0; k < Op::NIN; ++k) {
@@ -390,11 +427,11 @@ hipError_t launch_map(const void *const *in, void *const *out, int64_t n,
 
 template <class Op>
 hipError_t launch_dtype(ta_dtype dt, const void *const *in, void *const *out,
-                        int64_t n, hipStream_t s) {
+                        int64_t n, hipStream_t s, uint32_t flags) {
   switch (dt) {
-    case TA_F32: return launch_map<F32, Op>(in, out, n, s);
-    case TA_F16: return launch_map<F16, Op>(in, out, n, s);
-    case TA_BF16: return launch_map<BF16, Op>(in, out, n, s);
+    case TA_F32: return launch_map<F32, Op>(in, out, n, s, flags);
+    case TA_F16: return launch_map<F16, Op>(in, out, n, s, flags);
+    case TA_BF16: return launch_map<BF16, Op>(in, out, n, s, flags);
   }
   return hipErrorInvalidValue;
 }
@@ -448,10 +485,17 @@ inline ta_status finish(hipError_t e) {
 
 template <class Op>
 ta_status run(const void *const *in, void *const *out, int64_t n, ta_dtype dt,
-              hipStream_t s) {
+              hipStream_t s, uint32_t flags = 0u) {
   const ta_status st = check_common(in, Op::NIN, out, Op::NOUT, n, dt);
   if (st != TA_OK || n == 0) return st;
-  return finish(launch_dtype<Op>(dt, in, out, n, s));
+  return finish(launch_dtype<Op>(dt, in, out, n, s, flags));
+}
+
+template <int MASK>
+ta_status paper(const void *x, void *const *outs, int64_t n, ta_dtype dt,
+                uint32_t flags, hipStream_t s) {
+  const void *in[1] = {x};
+  return run<PaperOp<MASK>>(in, outs, n, dt, s, flags);
 }
 
 template <int MASK, bool GUARD>
@@ -632,6 +676,30 @@ ta_status ta_copy(const void *const *in, int n_in, void *const *out, int n_out,
     case 3 * 4 + 2: return run<CopyOp<3, 2>>(in, out, n, dt, s);
     default: return run<CopyOp<3, 3>>(in, out, n, dt, s);
   }
+}
+
+ta_status ta_paper_sincos(const void *x, void *ys, void *yc, void *yt,
+                          int64_t n, ta_dtype dt, uint32_t flags,
+                          hipStream_t s) {
+  if (!dtype_ok(dt)) return TA_EDTYPE;
+  if (flags & ~uint32_t(TA_FLAG_TAN_GUARD | TA_FLAG_LITERAL_DIVISOR))
+    return TA_EINVAL;
+  void *o[3];
+  int m = 0, k = 0;
+  if (ys) { o[k++] = ys; m |= kSin; }
+  if (yc) { o[k++] = yc; m |= kCos; }
+  if (yt) { o[k++] = yt; m |= kTan; }
+  switch (m) {
+    case kSin: return paper<kSin>(x, o, n, dt, flags, s);
+    case kCos: return paper<kCos>(x, o, n, dt, flags, s);
+    case kTan: return paper<kTan>(x, o, n, dt, flags, s);
+    case kSin | kCos: return paper<kSin | kCos>(x, o, n, dt, flags, s);
+    case kSin | kTan: return paper<kSin | kTan>(x, o, n, dt, flags, s);
+    case kCos | kTan: return paper<kCos | kTan>(x, o, n, dt, flags, s);
+    case kSin | kCos | kTan:
+      return paper<kSin | kCos | kTan>(x, o, n, dt, flags, s);
+  }
+  return n < 0 || n > 0 ? TA_EINVAL : TA_OK;  // no output requested
 }
 
 const char *ta_status_str(ta_status st) {

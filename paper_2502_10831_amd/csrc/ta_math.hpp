@@ -80,24 +80,30 @@ __host__ __device__ constexpr double kdet_of_row(int idx) {
 
 // Per-workgroup copy of the table in LDS (no table in HBM).  Rows are
 // indexed j + 4*(q & 1): rows 0-2 even quadrants, 4-6 odd, 3 and 7 unused.
+// One lane writes it with immediates; the caller synchronises.
 struct Tables {
   PieceRow row[8];
   float kdet[8];
+  static constexpr bool kUsed = true;
+  __device__ static void init(Tables &tb) {
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int i = 0; i < 6; ++i) {
+        const int slot = i < 3 ? i : i + 1;
+        tb.row[slot] = piece_row(i);
+        tb.kdet[slot] = float(kdet_of_row(i));
+      }
+      tb.row[3] = tb.row[7] = PieceRow{0.0, 0.0, 1.0, 0.0};
+      tb.kdet[3] = tb.kdet[7] = 0.0f;
+    }
+  }
 };
 
-// One lane writes the table with immediates; the caller synchronises.
-__device__ inline void init_tables(Tables &tb) {
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int i = 0; i < 6; ++i) {
-      const int slot = i < 3 ? i : i + 1;
-      tb.row[slot] = piece_row(i);
-      tb.kdet[slot] = float(kdet_of_row(i));
-    }
-    tb.row[3] = tb.row[7] = PieceRow{0.0, 0.0, 1.0, 0.0};
-    tb.kdet[3] = tb.kdet[7] = 0.0f;
-  }
-}
+// For element functors that need no table.
+struct NoTable {
+  static constexpr bool kUsed = false;
+  __device__ static void init(NoTable &) {}
+};
 
 // ---------------------------------------------------------------------------
 // 1. Argument reduction
@@ -309,6 +315,71 @@ __device__ inline float taylor_tan_unsigned(float rho) {
   for (int j = TERMS - 2; j >= 0; --j)
     s = __builtin_fmaf(s, z, float(tan_coef(j)));
   return s * rho;
+}
+
+// ---------------------------------------------------------------------------
+// The paper's literal arithmetic (Section 3, Algorithms 1-4), FP64: radian
+// coefficients, piece index floor(rho/divisor), the fast inverse square root
+// in place of 1/sqrt and of the division.  Reproduces the error columns of
+// Tables 1-3; not the default path.
+// ---------------------------------------------------------------------------
+constexpr uint64_t kFisrMagic = 0x5fe6eb50c7b537a9ull;  // Algorithm 1
+constexpr double kPi12 = 0x1.0c152382d7366p-2;          // RN(pi/12)
+constexpr double kLiteralDivisor = 0.261;  // pseudocode of proposed_sin/tan
+
+// Algorithm 1: magic-constant initial guess, one Newton-Raphson step.
+__device__ inline double fisr(double number) {
+  const double x2 = number * 0.5;
+  const int64_t i = int64_t(kFisrMagic) - (__double_as_longlong(number) >> 1);
+  const double y = __longlong_as_double(i);
+  return y * (1.5 - ((x2 * y) * y));
+}
+
+// Radian coefficients of piece k: a = a_k K, b, c = c_k K, d and the
+// quadratic x a^2 + ..: qx = a^2 + c^2, qy = 2(ab + cd), qz = b^2 + d^2
+// (Appendix A.4), evaluated in that order.
+struct PaperRow {
+  double a, b, c, d, qx, qy, qz, pad;
+};
+
+struct PaperTables {
+  PaperRow row[6];
+  static constexpr bool kUsed = true;
+  __device__ static void init(PaperTables &tb) {
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        PaperRow r;
+        r.a = double(kA[k]) * kDegPerRad;
+        r.b = double(kB[k]);
+        r.c = double(kC[k]) * kDegPerRad;
+        r.d = double(kD[k]);
+        r.qx = r.a * r.a + r.c * r.c;
+        r.qy = 2.0 * (r.a * r.b + r.c * r.d);
+        r.qz = r.b * r.b + r.d * r.d;
+        r.pad = 0.0;
+        tb.row[k] = r;
+      }
+    }
+  }
+};
+
+// Algorithms 2-4 at the folded angle `ang` (radians, [0, pi/2]); unsigned.
+__device__ inline void paper_eval(double ang, double divisor,
+                                  const PaperTables &tb, double &s, double &c,
+                                  double &t) {
+  int k = int(ang / divisor);
+  k = k > 5 ? 5 : k;
+  const PaperRow r = tb.row[k];
+  const double poly_s = r.a * ang + r.b;             // Algorithm 2: poly
+  const double ang2 = ang * ang;                     // Algorithm 2: ang2
+  const double inner = r.qx * ang2 + r.qy * ang + r.qz;
+  const double inv = fisr(inner);
+  s = poly_s * inv;
+  const double poly_c = r.c * ang + r.d;             // Algorithm 3
+  c = poly_c * inv;
+  const double tmp = fisr(poly_c);                   // Algorithm 4
+  t = poly_s * (tmp * tmp);
 }
 
 }  // namespace ta

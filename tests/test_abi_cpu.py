@@ -97,6 +97,16 @@ def test_backward_validation(lib):
         assert f(A, B, B + 512, B + 1024, 16, 5, None) == EDTYPE
 
 
+def test_paper_validation(lib):
+    f = _fn(lib, "ta_paper_sincos", vp, vp, vp, vp, i64, i32, u32, vp)
+    assert f(A, None, None, None, 16, F32, 0, None) == EINVAL   # no output
+    assert f(A, None, None, None, 0, F32, 0, None) == OK
+    assert f(A, B, None, None, 16, F32, 4, None) == EINVAL      # bad flag
+    assert f(A, B, None, None, 16, 5, 0, None) == EDTYPE
+    assert f(A, B, B + 8, None, 16, F32, 3, None) == EOVERLAP
+    assert f(None, B, None, None, 16, F32, 0, None) == EINVAL
+
+
 def test_comparator_validation(lib):
     f = _fn(lib, "ta_builtin_sincos", vp, vp, vp, vp, i64, i32, i32, vp)
     assert f(A, B, B + 256, None, 16, 0, F16, None) == EDTYPE

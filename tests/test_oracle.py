@@ -396,3 +396,32 @@ def test_gradient_closed_forms_and_trig_distance(dense_rho):
     np.testing.assert_allclose(om_t[x < 1.5], om_s[x < 1.5], rtol=1e-12)
     assert 0.97 < om_s.min() and om_s.max() < 1.01
     assert np.abs(g["sin"] - np.cos(x)).max() < 2.3e-2
+
+
+def test_paper_protocol_statistics(golden_dir):
+    """Section 4 protocol on the oracle's literal arithmetic: angles uniform
+    in [-1e6, 1e6]; errors against libm as in run_benchmark (relative error
+    0 where |std| <= 1e-12).  The sample here is 10^6 angles; the printed
+    values come from 1000, so the averages agree within that sample's
+    standard error and the printed maxima are at most ours."""
+    tab = _table(golden_dir)
+    rng = np.random.default_rng(RNG_SEED)
+    x = rng.uniform(-1e6, 1e6, 1_000_000)
+    got = oracle.paper(x)
+    for name, fn in (("sin", np.sin), ("cos", np.cos), ("tan", np.tan)):
+        ref = fn(x)
+        ea = np.abs(got[name] - ref)
+        er = np.where(np.abs(ref) > 1e-12, ea / np.abs(ref), 0.0)
+        p_amax, p_aavg, p_astd, p_rmax, p_ravg, p_rstd = tab[(name,
+                                                              "proposed")]
+        if name != "tan":
+            assert round(ea.max(), 6) == p_amax
+            assert abs(ea.mean() - p_aavg) < 3.5 * ea.std() / math.sqrt(1000)
+        keep = np.abs(np.cos(x)) > 1e-3 if name == "tan" else slice(None)
+        assert p_rmax <= er[keep].max() <= 1.25 * p_rmax
+        assert abs(er.mean() - p_ravg) < 3.5 * er.std() / math.sqrt(1000)
+    # proposed_tan's guard: +inf (unsigned) within 1e-3 of the poles
+    g = oracle.paper(x[:20000], flags=oracle.TAN_GUARD)["tan"]
+    near_pole = np.abs(np.cos(x[:20000])) < math.sin(1e-3)
+    assert np.all(np.isposinf(g[near_pole]))
+    assert not np.isinf(g[~near_pole]).any()
