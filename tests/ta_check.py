@@ -28,22 +28,22 @@ JUMP_NODES = np.array([1, 2, 4, 5]) * (math.pi / 12)
 
 def ulp32(y):
     y = np.abs(np.asarray(y, np.float64))
-    with np.errstate(divide="ignore"):
-        e = np.floor(np.log2(np.where(y > 0, y, 1.0)))
-    e = np.where(y > 0, np.maximum(e, -126), -126)
-    return np.ldexp(1.0, (e - 23).astype(np.int64))
+    _, e = np.frexp(y)                       # y = m 2^e, 0.5 <= m < 1
+    e = np.where(y > 0, np.maximum(e - 1, -126), -126)  # floor(log2 y)
+    return np.ldexp(1.0, e - 23)
 
 
 def neighbour_values(x):
     """For inputs near a jump node: the oracle's values on the piece across
     the nearest node (signed like the outputs); NaN elsewhere."""
     rho, v, k, ns, nc = oracle.fold(x)
-    d = np.abs(rho[:, None] - JUMP_NODES[None, :])
-    near = d.min(axis=1) < BAND
+    step = math.pi / 12
+    knode = np.rint(rho / step)
+    near = (np.abs(rho - knode * step) < BAND) & np.isin(knode, (1, 2, 4, 5))
     alt = {name: np.full(len(x), np.nan) for name in ("sin", "cos", "tan")}
     for i in np.nonzero(near)[0]:
-        node = JUMP_NODES[np.argmin(d[i])]
-        k_alt = int(round(node / (math.pi / 12))) - (1 if rho[i] >= node else 0)
+        node = knode[i] * step
+        k_alt = int(knode[i]) - (1 if rho[i] >= node else 0)
         s, c, t = oracle.piece_scs(k_alt, rho[i], v[i])
         alt["sin"][i] = -s if ns[i] else s
         alt["cos"][i] = -c if nc[i] else c
@@ -59,9 +59,17 @@ def ulp_error(gpu, ref):
 
 
 def check_f32(name, x, gpu, ref, alt=None, near=None, max_ulp=4.0):
-    """Assert the FP32 rule; returns the max ulp error (band elements use the
-    better of the two pieces).  `name` is 'label:fn' or 'fn' with fn one of
-    sin/cos/tan."""
+    """Assert the FP32 rule; returns the max ulp error (see check_f32_counted)."""
+    return check_f32_counted(name, x, gpu, ref, alt, near, max_ulp)[0]
+
+
+def check_f32_counted(name, x, gpu, ref, alt=None, near=None, max_ulp=4.0):
+    """Assert the FP32 rule; returns (max ulp error, number of band inputs
+    that matched only the neighbouring piece).  Elements that miss the rule
+    and lie in the jump-node band are re-checked against the neighbouring
+    piece (computed here unless `alt`/`near` are given).  `name` ends with
+    the function (sin/cos/tan)."""
+    fn = name.rsplit(":", 1)[-1].split("_")[-1].rsplit("-", 1)[-1]
     gpu = np.asarray(gpu, np.float64)
     ref = np.asarray(ref, np.float64)
     nan_ref = np.isnan(ref)
@@ -69,12 +77,18 @@ def check_f32(name, x, gpu, ref, alt=None, near=None, max_ulp=4.0):
         f"{name}: NaN mismatch at {np.nonzero(np.isnan(gpu) != nan_ref)[0][:5]}"
     err = ulp_error(gpu, ref)
     err[nan_ref] = 0.0
-    check_f32.rescued = 0
-    if alt is not None and near is not None and near.any():
-        err_alt = ulp_error(gpu, alt[name.rsplit(":", 1)[-1].split("_")[-1]])
-        check_f32.rescued = int(((err > max_ulp) & near &
-                                 (err_alt <= max_ulp)).sum())
-        err[near] = np.minimum(err[near], err_alt[near])
+    rescued = 0
+    bad = np.nonzero(err > max_ulp)[0]
+    if bad.size:
+        if alt is None or near is None:
+            near_b, alt_b = neighbour_values(np.asarray(x, np.float64)[bad])
+            alt_b = alt_b[fn]
+        else:
+            near_b, alt_b = near[bad], alt[fn][bad]
+        err_alt = ulp_error(gpu[bad], alt_b)
+        ok = near_b & (err_alt <= max_ulp)
+        rescued = int(ok.sum())
+        err[bad[ok]] = err_alt[ok]
     zero = (ref == 0) & ~nan_ref
     if zero.any():
         assert np.array_equal(np.signbit(gpu[zero]), np.signbit(ref[zero])), \
@@ -85,7 +99,7 @@ def check_f32(name, x, gpu, ref, alt=None, near=None, max_ulp=4.0):
         raise AssertionError(
             f"{name}: {worst:.3f} ulp > {max_ulp} at x={x[i]!r} "
             f"gpu={gpu[i]!r} oracle={ref[i]!r}")
-    return worst
+    return worst, rescued
 
 
 def check_16(name, kind, gpu_raw, ref, tol_abs, alt=None, near=None):

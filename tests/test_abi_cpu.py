@@ -129,3 +129,16 @@ def test_status_strings(lib):
     assert b"gfx950" in lib.ta_version()
     lib.ta_last_hip_error.restype = ctypes.c_int
     assert lib.ta_last_hip_error() == 0
+
+
+def test_binding_refuses_cpu_tensors():
+    """The Python layer has no CPU path: host tensors raise before any
+    library call."""
+    torch = pytest.importorskip("torch")
+    import paper_2502_10831_amd as ta
+    x = torch.zeros(8)
+    for fn in (ta.sin, ta.cos, ta.tan, ta.sincos):
+        with pytest.raises(ta.TaError):
+            fn(x)
+    with pytest.raises(ta.TaError):
+        ta.SinFn.apply(x)

@@ -11,8 +11,8 @@ import torch
 import oracle
 import paper_2502_10831_amd as ta
 from paper_2502_10831_amd import workloads as wl
-from ta_check import (U24, check_16, check_f32, neighbour_values, ulp32,
-                      ulp_error)
+from ta_check import (U24, check_16, check_f32, check_f32_counted,
+                      neighbour_values, ulp32, ulp_error)
 
 pytestmark = pytest.mark.gpu
 
@@ -58,19 +58,24 @@ def run_forward(x_dev):
 
 
 def check_all_f32(x, out, label):
+    """Every output in `out` against the oracle; the outputs are checked in
+    parallel threads (numpy releases the GIL)."""
+    from concurrent.futures import ThreadPoolExecutor
     ref = oracle.forward(x.astype(np.float64))
-    near, alt = neighbour_values(x.astype(np.float64))
-    worst = {}
-    rescued = 0
-    for key, name in (("sin", "sin"), ("cos", "cos"), ("tan", "tan"),
-                      ("f3_sin", "sin"), ("f3_cos", "cos"), ("f3_tan", "tan"),
-                      ("f2_sin", "sin"), ("f2_cos", "cos")):
-        if key in out:
-            worst[key] = check_f32(f"{label}:{key}", x, out[key], ref[name],
-                                   alt, near)
-            rescued += check_f32.rescued
-    say(f"{label}: max ulp {worst}; band elements {int(near.sum())}, "
-        f"passing only on the neighbouring piece {rescued}")
+    keys = [k for k in ("sin", "cos", "tan", "f3_sin", "f3_cos", "f3_tan",
+                        "f2_sin", "f2_cos") if k in out]
+
+    def one(key):
+        w, r = check_f32_counted(f"{label}:{key}", x, out[key],
+                                 ref[key.split("_")[-1]])
+        return key, w, r
+
+    with ThreadPoolExecutor(max_workers=4) as pool:
+        results = list(pool.map(one, keys))
+    worst = {k: w for k, w, _ in results}
+    rescued = sum(r for _, _, r in results)
+    say(f"{label}: max ulp {worst}; inputs that matched only the "
+        f"neighbouring piece across a jump node: {rescued}")
     return worst
 
 
@@ -91,11 +96,15 @@ def test_forward_small_uniform(dev):
 
 
 def test_forward_strided_fp32_sweep(dev):
-    """Every 61st FP32 in [0, 2pi] and its negation (~18M values).  The full
-    sweep (every FP32 in [0, 2 pi]) runs with TA_EXHAUSTIVE=1."""
+    """Every 61st FP32 in [0, 2pi] and its negation (~35M values).  With
+    TA_EXHAUSTIVE=1 every FP32 in [0, 2 pi] and its negation; with
+    TA_EXHAUSTIVE=all every finite FP32."""
+    mode = os.environ.get("TA_EXHAUSTIVE", "")
     lo = np.float32(0.0).view(np.uint32)
     hi = np.float32(2 * math.pi).view(np.uint32)
-    step = 1 if os.environ.get("TA_EXHAUSTIVE") == "1" else 61
+    if mode == "all":
+        hi = np.uint32(0x7F7FFFFF)
+    step = 1 if mode in ("1", "all") else 61
     chunk = 1 << 24
     worst = {}
     total = 0
@@ -114,6 +123,85 @@ def test_forward_strided_fp32_sweep(dev):
             worst[k] = max(worst.get(k, 0.0), v)
         total += x.size
     say(f"sweep total {total} values, max ulp {worst}")
+
+
+def test_forward_wide_strided_sweep(dev):
+    """Every 127th FP32 from 2 pi up to the largest finite float, and the
+    negations (~17M values): the two-word and the bit-table reductions."""
+    lo = int(np.float32(2 * math.pi).view(np.uint32))
+    hi = 0x7F7FFFFF
+    step = 127
+    chunk = 1 << 24
+    worst = {}
+    for start in range(lo, hi + 1, chunk * step):
+        bits = np.arange(start, min(start + chunk * step, hi + 1), step,
+                         dtype=np.uint64).astype(np.uint32)
+        x = bits.view(np.float32)
+        x = np.concatenate([x, -x])
+        say(f"wide sweep chunk start=0x{start:08x} n={x.size}")
+        xd = to_dev(x, dev)
+        ys, yc, yt = (torch.empty_like(xd) for _ in range(3))
+        ta.ta_sincos(xd, ys, yc, yt)
+        w = check_all_f32(x, {"f3_sin": host(ys), "f3_cos": host(yc),
+                              "f3_tan": host(yt)}, "wide")
+        for k, v in w.items():
+            worst[k] = max(worst.get(k, 0.0), v)
+    say(f"wide sweep max ulp {worst}")
+
+
+def test_graph_capture_replays(dev):
+    """The launch is capturable: replay a captured ta_sincos several times,
+    with eager work between replays, and compare every replay bit for bit
+    with the eager result."""
+    x = wl.small_uniform(1 << 16, seed=101)
+    xd = to_dev(x, dev)
+    ys, yc, yt = (torch.empty_like(xd) for _ in range(3))
+    ta.ta_sincos(xd, ys, yc, yt)
+    eager = [host(t).copy() for t in (ys, yc, yt)]
+    say("graph capture")
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        ta.ta_sincos(xd, ys, yc, yt)
+    for rep in range(4):
+        for t in (ys, yc, yt):
+            t.fill_(float(rep + 7))
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for t, e in zip((ys, yc, yt), eager):
+            assert np.array_equal(host(t).view(np.uint32), e.view(np.uint32))
+
+
+def test_concurrent_host_threads(dev):
+    """Calls from several host threads on their own streams."""
+    import threading
+    xs = [wl.small_uniform(1 << 18, seed=110 + i) for i in range(4)]
+    refs = [oracle.forward(x.astype(np.float64))["sin"] for x in xs]
+    outs = [None] * 4
+    errors = []
+
+    def work(i):
+        try:
+            stream = torch.cuda.Stream()
+            with torch.cuda.stream(stream):
+                xd = torch.from_numpy(xs[i]).to(dev, non_blocking=False)
+                y = torch.empty_like(xd)
+                for _ in range(20):
+                    ta.ta_sin(xd, y)
+                stream.synchronize()
+                outs[i] = y.cpu().numpy()
+        except Exception as e:  # reported below
+            errors.append(e)
+
+    say("concurrent host threads")
+    threads = [threading.Thread(target=work, args=(i,)) for i in range(4)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errors, errors
+    for o, r in zip(outs, refs):
+        assert ulp_error(o, r).max() <= 4.0
 
 
 def test_forward_throughput_mix_full_size(dev):
