@@ -56,7 +56,10 @@ constexpr int kD[6] = {632, 657, 541, 1252, 910, 990};
 // and with t = a (the complement) N = (90 a_k + b_k) - a_k t and
 // D = (90 c_k + d_k) - c_k t.
 struct PieceRow {
-  double iN, sN, iD, sD;  // N = iN + sN t, D = iD + sD t (t in degrees)
+  // N = iN + sN a, D = iD + sD a with a = |r| in radians: the integer slopes
+  // times 180/pi, rounded once in FP64 (a 2^-53 relative change of the
+  // slope; the degree conversion of a is folded into it)
+  double iN, sN, iD, sD;
 };
 
 __host__ __device__ constexpr int piece_of_row(int idx) {
@@ -65,10 +68,12 @@ __host__ __device__ constexpr int piece_of_row(int idx) {
 
 __host__ __device__ constexpr PieceRow piece_row(int idx) {
   const int k = piece_of_row(idx);
-  return idx < 3 ? PieceRow{double(kB[k]), double(kA[k]), double(kD[k]),
-                            double(kC[k])}
-                 : PieceRow{double(90 * kA[k] + kB[k]), double(-kA[k]),
-                            double(90 * kC[k] + kD[k]), double(-kC[k])};
+  return idx < 3 ? PieceRow{double(kB[k]), double(kA[k]) * kDegPerRad,
+                            double(kD[k]), double(kC[k]) * kDegPerRad}
+                 : PieceRow{double(90 * kA[k] + kB[k]),
+                            double(-kA[k]) * kDegPerRad,
+                            double(90 * kC[k] + kD[k]),
+                            double(-kC[k]) * kDegPerRad};
 }
 
 // (180/pi) * (a_k d_k - b_k c_k): d(tan piece)/d rho = this / D^2, and the
@@ -161,7 +166,11 @@ __device__ inline void reduce_large(float x, double &r, uint32_t &q) {
 // r and the low bits of q (two's complement) for any float x.
 __device__ inline void reduce(float x, double &r, uint32_t &q) {
   const double xd = double(x);
-  const double qb = __builtin_fma(xd, kTwoOverPi, kRoundMagic);
+  // q = round(x 2/pi) by adding 1.5 2^52 (the product is rounded first: an
+  // x within an ulp of a half-integer multiple of pi/4 may get the other
+  // neighbour and |r| up to pi/4 (1 + 2^-50), where pieces 2 and 3 meet
+  // continuously)
+  const double qb = xd * kTwoOverPi + kRoundMagic;
   const double qd = qb - kRoundMagic;  // +0 when q = 0, so r keeps x's zero
   q = uint32_t(__double2loint(qb));    // low word of the mantissa = q
   double rr = __builtin_fma(-qd, kPio2Hi, xd);  // exact
@@ -170,9 +179,11 @@ __device__ inline void reduce(float x, double &r, uint32_t &q) {
 }
 
 // Folded element: everything the later stages need.
+constexpr double kPi12 = 0x1.0c152382d7366p-2;  // RN(pi/12)
+constexpr double kPi6 = 0x1.0c152382d7366p-1;   // RN(pi/6)
+
 struct Folded {
-  double t;       // |r| in degrees, [0, 45]
-  double a;       // |r| in radians
+  double a;       // |r| in radians, [0, pi/4]
   uint32_t q;     // quadrant, low bits
   uint32_t hr;    // high word of r: bit 31 = sign of r
   uint32_t row;   // LDS table slot j + 4*(q & 1)
@@ -185,9 +196,8 @@ __device__ inline Folded fold(float x) {
   Folded f;
   f.hr = uint32_t(__double2hiint(r));
   f.a = __builtin_fabs(r);
-  f.t = f.a * kDegPerRad;
   // j = 15-degree slot of |r|; the family (q & 1) selects slots 4..6
-  const uint32_t j = f.t >= 30.0 ? 2u : (f.t >= 15.0 ? 1u : 0u);
+  const uint32_t j = f.a >= kPi6 ? 2u : (f.a >= kPi12 ? 1u : 0u);
   f.q = q;
   f.row = ((q << 2) & 4u) | j;
   return f;
@@ -226,8 +236,8 @@ struct Forms {
 
 __device__ inline Forms forms(const Folded &f, const Tables &tb) {
   const PieceRow c = tb.row[f.row];
-  const double nd = __builtin_fma(c.sN, f.t, c.iN);
-  const double dd = __builtin_fma(c.sD, f.t, c.iD);
+  const double nd = __builtin_fma(c.sN, f.a, c.iN);
+  const double dd = __builtin_fma(c.sD, f.a, c.iD);
   const double qd = __builtin_fma(nd, nd, dd * dd);
   return Forms{float(nd), float(dd), float(qd)};
 }
@@ -324,7 +334,6 @@ __device__ inline float taylor_tan_unsigned(float rho) {
 // Tables 1-3; not the default path.
 // ---------------------------------------------------------------------------
 constexpr uint64_t kFisrMagic = 0x5fe6eb50c7b537a9ull;  // Algorithm 1
-constexpr double kPi12 = 0x1.0c152382d7366p-2;          // RN(pi/12)
 constexpr double kLiteralDivisor = 0.261;  // pseudocode of proposed_sin/tan
 
 // Algorithm 1: magic-constant initial guess, one Newton-Raphson step.

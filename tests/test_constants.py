@@ -33,6 +33,8 @@ def test_reduction_constants(text):
     assert _const(text, "kPio2Lo") == float(pi / 2 - mpmath.mpf(hi))
     assert _const(text, "kDegPerRad") == float(180 / pi)
     assert _const(text, "kRoundMagic") == 1.5 * 2.0 ** 52
+    assert _const(text, "kPi12") == float(pi / 12)
+    assert _const(text, "kPi6") == float(pi / 6)
 
 
 def test_two_over_pi_bits(text):
