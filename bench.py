@@ -263,6 +263,21 @@ def comparators(x, x_host, n, args, torch, ta, np):
     res["ta_sin"] = {"gelem_s": round(n / (ms * 1e-3) / 1e9, 2),
                      "gbs": round(8 * n / (ms * 1e-3) / 1e9, 1)}
 
+    ne, nf = 1 << 24, 8
+    xe = x[:ne]
+    ye = torch.empty(2 * nf * ne, device=x.device)
+
+    def fe():
+        ta.ta_sincos_encode(xe, ye, nf)
+    log("timing ta_sincos_encode (8 frequencies)")
+    per, total, _ = time_launches(fe, args.steps, args.warmup, torch)
+    ms = total / args.steps
+    res["ta_sincos_encode_8freq"] = {
+        "n": ne, "gelem_s": round(ne / (ms * 1e-3) / 1e9, 2),
+        "outputs_per_s_G": round(2 * nf * ne / (ms * 1e-3) / 1e9, 1),
+        "gbs_algorithmic": round((4 + 8 * nf) * ne / (ms * 1e-3) / 1e9, 1)}
+    del ye
+
     def fc():
         ta.ta_copy([x], [ys, yc, yt])
     per, total, _ = time_launches(fc, args.steps, args.warmup, torch)

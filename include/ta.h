@@ -142,6 +142,18 @@ ta_status ta_paper_sincos(const void *x, void *ys, void *yc, void *yt,
                           int64_t n, ta_dtype dt, uint32_t flags,
                           hipStream_t stream);
 
+/* ---- multi-frequency encoding (an application of the fused core) --------
+ * For j = 0 .. nfreq-1 (1 <= nfreq <= 16), with y holding 2*nfreq planes of n
+ * elements each (plane-major):
+ *   y[(2j) n + i] = sin_a(2^j x[i]),   y[(2j+1) n + i] = cos_a(2^j x[i]).
+ * One read of x, one reduction and one pair of linear forms per frequency,
+ * same accuracy as ta_sincos on the argument 2^j x (exact in FP32; it
+ * overflows to +-Inf, giving NaN, only for |x| >= 2^(128-j)).  y must not
+ * overlap x.  16-byte accesses when x and y share their address modulo 16 and
+ * n * sizeof(dtype) is a multiple of 16; a scalar kernel otherwise. */
+ta_status ta_sincos_encode(const void *x, void *y, int64_t n, int nfreq,
+                           ta_dtype dt, hipStream_t stream);
+
 /* ---- measurement comparators (not part of the method) -------------------
  * The same load/store skeleton around the GPU's built-in functions:
  *   kind 0: sinf / cosf / tanf (accurate device library)

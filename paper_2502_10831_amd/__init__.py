@@ -27,10 +27,10 @@ __all__ = [
     "ta_taylor_sin", "ta_taylor_cos", "ta_taylor_tan",
     "ta_sin_bwd", "ta_cos_bwd", "ta_tan_bwd", "ta_sincos_bwd",
     "ta_sin_fwdbwd", "ta_cos_fwdbwd", "ta_tan_fwdbwd",
-    "ta_paper_sincos", "ta_builtin_sincos", "ta_copy",
+    "ta_paper_sincos", "ta_sincos_encode", "ta_builtin_sincos", "ta_copy",
     "sin", "cos", "tan", "sincos", "taylor",
     "SinFn", "CosFn", "TanFn", "SinCosFn",
-    "TA_FLAG_TAN_GUARD", "TA_FLAG_LITERAL_DIVISOR", "paper_sincos",
+    "TA_FLAG_TAN_GUARD", "TA_FLAG_LITERAL_DIVISOR", "paper_sincos", "encode",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -83,6 +83,7 @@ def load(path: str | None = None):
         "ta_cos_fwdbwd": [vp, vp, vp, vp, i64, i32, vp],
         "ta_tan_fwdbwd": [vp, vp, vp, vp, i64, i32, vp],
         "ta_paper_sincos": [vp, vp, vp, vp, i64, i32, u32, vp],
+        "ta_sincos_encode": [vp, vp, i64, i32, i32, vp],
         "ta_builtin_sincos": [vp, vp, vp, vp, i64, i32, i32, vp],
         "ta_copy": [ctypes.POINTER(vp), i32, ctypes.POINTER(vp), i32, i64,
                     i32, vp],
@@ -249,6 +250,17 @@ def ta_paper_sincos(x, ys=None, yc=None, yt=None, flags: int = 0):
                                   dt, int(flags), s))
 
 
+def ta_sincos_encode(x, y, nfreq: int):
+    """y (2*nfreq*x.numel() elements, plane-major): plane 2j = sin_a(2^j x),
+    plane 2j+1 = cos_a(2^j x)."""
+    _dev(x, "x"); _dev(y, "y")
+    if y.dtype != x.dtype or y.device != x.device or \
+            y.numel() != 2 * int(nfreq) * x.numel():
+        raise TaError("y must hold 2*nfreq*x.numel() elements of x's dtype")
+    n, dt, s = _args(x)
+    _check(load().ta_sincos_encode(_ptr(x), _ptr(y), n, int(nfreq), dt, s))
+
+
 def ta_builtin_sincos(x, ys, yc, yt=None, kind: int = 0):
     """Comparator: the GPU's built-in sinf/cosf/tanf (kind 0), __sinf/...
     (kind 1) or sincosf (kind 2) in the same streaming skeleton."""
@@ -308,6 +320,15 @@ def paper_sincos(x, guard: bool = False, literal_divisor: bool = False):
         (TA_FLAG_LITERAL_DIVISOR if literal_divisor else 0)
     ta_paper_sincos(x, ys, yc, yt, flags)
     return ys, yc, yt
+
+
+def encode(x, nfreq: int):
+    """Tensor [2*nfreq, *x.shape]: sin_a(2^j x), cos_a(2^j x) for j < nfreq."""
+    x = _c(x)
+    y = torch.empty((2 * int(nfreq),) + tuple(x.shape), dtype=x.dtype,
+                    device=x.device)
+    ta_sincos_encode(x, y, nfreq)
+    return y
 
 
 def taylor(x, fn: str, terms: int = 5):

@@ -78,7 +78,7 @@ struct FwdOp {
       float t = set_sign(div_refined(v.n, v.d), tan_mask(f));
       if constexpr (GUARD) {
         // Section 3 proposed_tan: +inf within 1e-3 of pi/2, before the sign.
-        if ((f.q & 1u) && f.a < 1e-3) t = __builtin_inff();
+        if ((f.q & 1u) && f.abs_r() < 1e-3) t = __builtin_inff();
       }
       out[o++] = t;
     }
@@ -170,7 +170,8 @@ struct PaperOp {
   __device__ static void apply(const float *in, float *out, const Table &tb,
                                uint32_t flags) {
     const Folded f = fold(in[0]);
-    const double ang = (f.q & 1u) ? (kPio2Hi - f.a) + kPio2Lo : f.a;
+    const double ang =
+        (f.q & 1u) ? (kPio2Hi - f.abs_r()) + kPio2Lo : f.abs_r();
     const double divisor =
         (flags & TA_FLAG_LITERAL_DIVISOR) ? kLiteralDivisor : kPi12;
     double s, c, t;
@@ -181,7 +182,7 @@ struct PaperOp {
     if constexpr (MASK & kTan) {
       float tt = flip_sign(float(t), tan_mask(f));
       // proposed_tan: +inf within 1e-3 of pi/2, before the sign
-      if ((flags & TA_FLAG_TAN_GUARD) && (f.q & 1u) && f.a < 1e-3)
+      if ((flags & TA_FLAG_TAN_GUARD) && (f.q & 1u) && f.abs_r() < 1e-3)
         tt = __builtin_inff();
       out[o++] = tt;
     }
@@ -369,6 +370,112 @@ __global__ __launch_bounds__(BLOCK) void map_vec_kernel(IoPtrs io, int64_t head,
     for (int64_t e = threadIdx.x; e < extra; e += BLOCK)
       scalar_element<ST, Op>(io, e < head ? e : tail0 + (e - head), tb);
   }
+}
+
+// Multi-frequency encoding: plane 2j holds sin_a(2^j x), plane 2j+1
+// cos_a(2^j x), j < nfreq, each plane n elements long.  One read of x, 2 nfreq
+// writes; 2^j x is exact in FP32 (it overflows to +-Inf, hence NaN, only for
+// |x| >= 2^(128-j)).  VEC_PATH: 16-byte accesses (every plane then starts
+// 16-byte aligned at element `head`), otherwise one element per lane.
+constexpr int kEncodeBlock = 256;
+template <class ST, bool VEC_PATH>
+__global__ __launch_bounds__(kEncodeBlock) void encode_kernel(
+    const char *x, char *y, int64_t n, int nfreq, int64_t head, int64_t nvec) {
+  using raw = typename ST::raw;
+  using Core = FwdOp<kSin | kCos, false>;
+  constexpr int VEC = VEC_PATH ? Vec<ST>::kElems : 1;
+  __shared__ Tables tb;
+  Tables::init(tb);
+  __syncthreads();
+  const int64_t plane = n * int64_t(sizeof(raw));
+  const int64_t v = int64_t(blockIdx.x) * kEncodeBlock + threadIdx.x;
+  if (v < nvec) {
+    float xf[VEC];
+    if constexpr (VEC_PATH) {
+      const u32x4 w = vload<false>(x + head * int64_t(sizeof(raw)), v);
+#pragma unroll
+      for (int e = 0; e < VEC; ++e)
+        xf[e] = ST::load(reinterpret_cast<const raw *>(&w)[e]);
+    } else {
+      xf[0] = ST::load(reinterpret_cast<const raw *>(x)[v]);
+    }
+    for (int j = 0; j < nfreq; ++j) {
+      float sv[VEC], cv[VEC];
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) {
+        const float in[1] = {xf[e] * __uint_as_float(uint32_t(127 + j) << 23)};
+        float out[2];
+        Core::apply(in, out, tb, 0u);
+        sv[e] = out[0];
+        cv[e] = out[1];
+      }
+      char *ps = y + (2 * j) * plane;
+      char *pc = ps + plane;
+      if constexpr (VEC_PATH) {
+        u32x4 ws, wc;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          if constexpr (VEC == 4) {
+            ws[k] = ST::store(sv[k]);
+            wc[k] = ST::store(cv[k]);
+          } else {
+            ws[k] = ST::store2(sv[2 * k], sv[2 * k + 1]);
+            wc[k] = ST::store2(cv[2 * k], cv[2 * k + 1]);
+          }
+        }
+        vstore<true>(ps + head * int64_t(sizeof(raw)), v, ws);
+        vstore<true>(pc + head * int64_t(sizeof(raw)), v, wc);
+      } else {
+        reinterpret_cast<raw *>(ps)[v] = ST::store(sv[0]);
+        reinterpret_cast<raw *>(pc)[v] = ST::store(cv[0]);
+      }
+    }
+  }
+  if (VEC_PATH && blockIdx.x == 0) {  // scalar head and tail
+    const int64_t tail0 = head + nvec * VEC;
+    const int64_t extra = head + (n - tail0);
+    for (int64_t e = threadIdx.x; e < extra; e += kEncodeBlock) {
+      const int64_t i = e < head ? e : tail0 + (e - head);
+      const float xi = ST::load(reinterpret_cast<const raw *>(x)[i]);
+      for (int j = 0; j < nfreq; ++j) {
+        const float in[1] = {xi * __uint_as_float(uint32_t(127 + j) << 23)};
+        float out[2];
+        Core::apply(in, out, tb, 0u);
+        reinterpret_cast<raw *>(y + (2 * j) * plane)[i] = ST::store(out[0]);
+        reinterpret_cast<raw *>(y + (2 * j + 1) * plane)[i] = ST::store(out[1]);
+      }
+    }
+  }
+}
+
+template <class ST>
+hipError_t launch_encode(const void *x, void *y, int64_t n, int nfreq,
+                         hipStream_t stream) {
+  using raw = typename ST::raw;
+  constexpr int VEC = Vec<ST>::kElems;
+  const uintptr_t mis = uintptr_t(x) & 15u;
+  const bool vec_ok = (uintptr_t(y) & 15u) == mis && mis % sizeof(raw) == 0 &&
+                      (n * int64_t(sizeof(raw))) % 16 == 0;
+  const char *xc = static_cast<const char *>(x);
+  char *yc = static_cast<char *>(y);
+  if (vec_ok) {
+    int64_t head = mis ? int64_t((16u - mis) / sizeof(raw)) : 0;
+    if (head > n) head = n;
+    const int64_t nvec = (n - head) / VEC;
+    int64_t blocks = (nvec + kEncodeBlock - 1) / kEncodeBlock;
+    if (blocks < 1) blocks = 1;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((encode_kernel<ST, true>), dim3(unsigned(blocks)),
+                       dim3(kEncodeBlock), 0, stream, xc, yc, n, nfreq, head,
+                       nvec);
+  } else {
+    const int64_t blocks = (n + kEncodeBlock - 1) / kEncodeBlock;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((encode_kernel<ST, false>), dim3(unsigned(blocks)),
+                       dim3(kEncodeBlock), 0, stream, xc, yc, n, nfreq,
+                       int64_t(0), n);
+  }
+  return hipGetLastError();
 }
 
 // Fallback when the buffers disagree on their address modulo 16.
@@ -700,6 +807,26 @@ ta_status ta_paper_sincos(const void *x, void *ys, void *yc, void *yt,
       return paper<kSin | kCos | kTan>(x, o, n, dt, flags, s);
   }
   return n < 0 || n > 0 ? TA_EINVAL : TA_OK;  // no output requested
+}
+
+ta_status ta_sincos_encode(const void *x, void *y, int64_t n, int nfreq,
+                           ta_dtype dt, hipStream_t s) {
+  if (!dtype_ok(dt)) return TA_EDTYPE;
+  if (n < 0 || nfreq < 1 || nfreq > 16) return TA_EINVAL;
+  if (n == 0) return TA_OK;
+  if (!x || !y) return TA_EINVAL;
+  const uintptr_t es = dtype_size(dt);
+  const uintptr_t xb = uintptr_t(x), yb = uintptr_t(y);
+  const uintptr_t xe = xb + uintptr_t(n) * es;
+  const uintptr_t ye = yb + uintptr_t(n) * es * uintptr_t(2 * nfreq);
+  if (xb < ye && yb < xe) return TA_EOVERLAP;
+  hipError_t e = hipErrorInvalidValue;
+  switch (dt) {
+    case TA_F32: e = launch_encode<F32>(x, y, n, nfreq, s); break;
+    case TA_F16: e = launch_encode<F16>(x, y, n, nfreq, s); break;
+    case TA_BF16: e = launch_encode<BF16>(x, y, n, nfreq, s); break;
+  }
+  return finish(e);
 }
 
 const char *ta_status_str(ta_status st) {

@@ -183,23 +183,22 @@ constexpr double kPi12 = 0x1.0c152382d7366p-2;  // RN(pi/12)
 constexpr double kPi6 = 0x1.0c152382d7366p-1;   // RN(pi/6)
 
 struct Folded {
-  double a;       // |r| in radians, [0, pi/4]
+  double r;       // reduced argument, |r| <= pi/4 (use abs_r())
   uint32_t q;     // quadrant, low bits
   uint32_t hr;    // high word of r: bit 31 = sign of r
   uint32_t row;   // LDS table slot j + 4*(q & 1)
+  // |r|, written at each use so that it folds into a source modifier
+  __device__ double abs_r() const { return __builtin_fabs(r); }
 };
 
 __device__ inline Folded fold(float x) {
-  double r;
-  uint32_t q;
-  reduce(x, r, q);
   Folded f;
-  f.hr = uint32_t(__double2hiint(r));
-  f.a = __builtin_fabs(r);
+  reduce(x, f.r, f.q);
+  f.hr = uint32_t(__double2hiint(f.r));
   // j = 15-degree slot of |r|; the family (q & 1) selects slots 4..6
-  const uint32_t j = f.a >= kPi6 ? 2u : (f.a >= kPi12 ? 1u : 0u);
-  f.q = q;
-  f.row = ((q << 2) & 4u) | j;
+  const uint32_t j =
+      f.abs_r() >= kPi6 ? 2u : (f.abs_r() >= kPi12 ? 1u : 0u);
+  f.row = ((f.q << 2) & 4u) | j;
   return f;
 }
 
@@ -236,8 +235,8 @@ struct Forms {
 
 __device__ inline Forms forms(const Folded &f, const Tables &tb) {
   const PieceRow c = tb.row[f.row];
-  const double nd = __builtin_fma(c.sN, f.a, c.iN);
-  const double dd = __builtin_fma(c.sD, f.a, c.iD);
+  const double nd = __builtin_fma(c.sN, f.abs_r(), c.iN);
+  const double dd = __builtin_fma(c.sD, f.abs_r(), c.iD);
   const double qd = __builtin_fma(nd, nd, dd * dd);
   return Forms{float(nd), float(dd), float(qd)};
 }
@@ -297,7 +296,7 @@ __host__ __device__ constexpr float cos_coef(int j) {
 
 // rho in FP32 from the fold: a for even q, pi/2 - a for odd q.
 __device__ inline float fold_rho(const Folded &f) {
-  const double rho = (f.q & 1u) ? (kPio2Hi - f.a) + kPio2Lo : f.a;
+  const double rho = (f.q & 1u) ? (kPio2Hi - f.abs_r()) + kPio2Lo : f.abs_r();
   return float(rho);
 }
 

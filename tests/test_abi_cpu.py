@@ -107,6 +107,19 @@ def test_paper_validation(lib):
     assert f(None, B, None, None, 16, F32, 0, None) == EINVAL
 
 
+def test_encode_validation(lib):
+    f = _fn(lib, "ta_sincos_encode", vp, vp, i64, i32, i32, vp)
+    for bad in (0, 17, -1):
+        assert f(A, B, 16, bad, F32, None) == EINVAL
+    assert f(A, B, -1, 4, F32, None) == EINVAL
+    assert f(A, B, 16, 4, 7, None) == EDTYPE
+    assert f(None, B, 16, 4, F32, None) == EINVAL
+    assert f(A, None, 16, 4, F32, None) == EINVAL
+    assert f(A, A + 32, 16, 4, F32, None) == EOVERLAP   # y starts inside x
+    assert f(B + 8, B, 16, 4, F32, None) == EOVERLAP    # x inside y's planes
+    assert f(A, B, 0, 4, F32, None) == OK
+
+
 def test_comparator_validation(lib):
     f = _fn(lib, "ta_builtin_sincos", vp, vp, vp, vp, i64, i32, i32, vp)
     assert f(A, B, B + 256, None, 16, 0, F16, None) == EDTYPE

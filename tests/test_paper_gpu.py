@@ -144,3 +144,28 @@ def test_paper_protocol_statistics_on_gpu(dev, golden_dir):
     say("GPU literal arithmetic vs libm (abs max, abs avg, rel max, rel avg): "
         + "; ".join(f"{k} " + ", ".join(f"{v:.6f}" for v in s)
                     for k, s in stats.items()))
+
+
+def test_taylor_tan_pole_study_on_gpu(dev, golden_dir):
+    """Table 3's Taylor columns share one worst angle (tan = abs/rel of the
+    Taylor-5 SIMD column); at the FP32 angle nearest to it the GPU Taylor-5/7/9
+    tan errors against FP64 libm reproduce the printed 153.496539 / 151.068956
+    / 148.681759 (the FP32 rounding of the angle moves tan by ~2e-3), while the
+    proposed tan stays within 0.4 of tan."""
+    rows = read_table(os.path.join(golden_dir, "table_error_statistics.txt"))
+    tab = {(r[0], r[1]): [float(v) for v in r[2:]] for r in rows}
+    a5, r5 = tab[("tan", "taylor5_simd")][0], tab[("tan", "taylor5_simd")][3]
+    x = np.array([math.atan(a5 / r5)], np.float32)
+    xd = torch.from_numpy(x).to(dev)
+    tan_ref = math.tan(float(x[0]))
+    say(f"Taylor tan pole study at x={x[0]!r}, tan={tan_ref:.4f}")
+    for terms, key in ((5, "taylor5_simd"), (7, "taylor7_simd"),
+                       (9, "taylor9_simd")):
+        y = torch.empty_like(xd)
+        ta.ta_taylor_tan(xd, y, terms)
+        err = tan_ref - float(y.cpu()[0])
+        say(f"Taylor-{terms} tan error {err:.4f} (printed {tab[('tan', key)][0]})")
+        assert abs(err - tab[("tan", key)][0]) < 6e-3
+    y = torch.empty_like(xd)
+    ta.ta_tan(xd, y)
+    assert abs(float(y.cpu()[0]) - tan_ref) < 0.4

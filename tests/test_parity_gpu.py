@@ -588,6 +588,54 @@ def test_fused_fwdbwd_full_size(dev):
 
 
 # ---------------------------------------------------------------------------
+# multi-frequency encoding
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [(1 << 18) + 4, 1000003])   # vector / scalar
+def test_encode_f32(dev, n):
+    nfreq = 8
+    x = wl.small_uniform(n, seed=121)
+    x[:3] = [0.0, -0.0, 1.5707964]
+    xd = to_dev(x, dev)
+    y = torch.empty(2 * nfreq * n, device=dev)
+    say(f"encode n={n} nfreq={nfreq}")
+    ta.ta_sincos_encode(xd, y, nfreq)
+    yh = host(y).reshape(2 * nfreq, n)
+    worst = 0.0
+    for j in range(nfreq):
+        xj = x.astype(np.float64) * 2.0 ** j
+        ref = oracle.forward(xj)
+        worst = max(worst,
+                    check_f32(f"enc{j}:sin", xj, yh[2 * j], ref["sin"]),
+                    check_f32(f"enc{j}:cos", xj, yh[2 * j + 1], ref["cos"]))
+    say(f"encode max ulp {worst}")
+    # frequency 0 is bit-identical to ta_sincos
+    ys, yc = torch.empty_like(xd), torch.empty_like(xd)
+    ta.ta_sincos(xd, ys, yc, None)
+    assert np.array_equal(host(ys).view(np.uint32), yh[0].view(np.uint32))
+    assert np.array_equal(host(yc).view(np.uint32), yh[1].view(np.uint32))
+
+
+@pytest.mark.parametrize("kind", ["f16", "bf16"])
+def test_encode_16bit_exhaustive(dev, kind):
+    tdt = torch.float16 if kind == "f16" else torch.bfloat16
+    raw = wl.all_16bit_patterns()
+    x64 = wl.decode_16(raw, kind)
+    nfreq = 4
+    say(f"encode 16-bit exhaustive {kind}")
+    xd = torch.from_numpy(raw.view(np.int16)).to(dev).view(tdt)
+    y = ta.encode(xd, nfreq)
+    got = host(y.view(torch.int16)).view(np.uint16)
+    for j in range(nfreq):
+        xj = x64 * 2.0 ** j
+        fin = np.abs(xj) < 3.0e38   # 2^j x stays finite in FP32
+        ref = oracle.forward(xj[fin])
+        for k, name in ((2 * j, "sin"), (2 * j + 1, "cos")):
+            check_16(f"enc{j}-{name}", kind, got[k][fin], ref[name],
+                     4 * ulp32(ref[name]))
+
+
+# ---------------------------------------------------------------------------
 # comparators and the copy ceiling kernel (not the method)
 # ---------------------------------------------------------------------------
 
