@@ -372,6 +372,23 @@ __global__ __launch_bounds__(BLOCK) void map_vec_kernel(IoPtrs io, int64_t head,
   }
 }
 
+// Launches `kernel` and returns the status of this launch itself (not a
+// sticky error left by earlier, unrelated calls).  The arguments are
+// converted to the kernel's own parameter types (non-deduced context), so
+// each slot of argv has exactly the size the kernel reads.
+template <typename T>
+struct Same {
+  using type = T;
+};
+template <typename... KArgs>
+hipError_t launch(void (*kernel)(KArgs...), int64_t blocks, int threads,
+                  hipStream_t stream, typename Same<KArgs>::type... args) {
+  void *argv[] = {static_cast<void *>(&args)...};
+  return hipLaunchKernel(reinterpret_cast<const void *>(kernel),
+                         dim3(unsigned(blocks)), dim3(unsigned(threads)), argv,
+                         0, stream);
+}
+
 // Multi-frequency encoding: plane 2j holds sin_a(2^j x), plane 2j+1
 // cos_a(2^j x), j < nfreq, each plane n elements long.  One read of x, 2 nfreq
 // writes; 2^j x is exact in FP32 (it overflows to +-Inf, hence NaN, only for
@@ -465,17 +482,14 @@ hipError_t launch_encode(const void *x, void *y, int64_t n, int nfreq,
     int64_t blocks = (nvec + kEncodeBlock - 1) / kEncodeBlock;
     if (blocks < 1) blocks = 1;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((encode_kernel<ST, true>), dim3(unsigned(blocks)),
-                       dim3(kEncodeBlock), 0, stream, xc, yc, n, nfreq, head,
-                       nvec);
+    return launch(encode_kernel<ST, true>, blocks, kEncodeBlock, stream, xc,
+                  yc, n, nfreq, head, nvec);
   } else {
     const int64_t blocks = (n + kEncodeBlock - 1) / kEncodeBlock;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((encode_kernel<ST, false>), dim3(unsigned(blocks)),
-                       dim3(kEncodeBlock), 0, stream, xc, yc, n, nfreq,
-                       int64_t(0), n);
+    return launch(encode_kernel<ST, false>, blocks, kEncodeBlock, stream, xc,
+                  yc, n, nfreq, int64_t(0), n);
   }
-  return hipGetLastError();
 }
 
 // Fallback when the buffers disagree on their address modulo 16.
@@ -520,16 +534,14 @@ hipError_t launch_map(const void *const *in, void *const *out, int64_t n,
     int64_t blocks = (nvec + per_block - 1) / per_block;
     if (blocks < 1) blocks = 1;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(
-        (map_vec_kernel<ST, Op, sh.block, sh.unroll, sh.nt_load, sh.nt_store>),
-        dim3(unsigned(blocks)), dim3(sh.block), 0, stream, io, head, nvec, n);
-  } else {
-    int64_t blocks = (n + kScalarBlock - 1) / kScalarBlock;
-    if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL((map_scalar_kernel<ST, Op>), dim3(unsigned(blocks)),
-                       dim3(kScalarBlock), 0, stream, io, n);
+    return launch(
+        map_vec_kernel<ST, Op, sh.block, sh.unroll, sh.nt_load, sh.nt_store>,
+        blocks, sh.block, stream, io, head, nvec, n);
   }
-  return hipGetLastError();
+  int64_t blocks = (n + kScalarBlock - 1) / kScalarBlock;
+  if (blocks > 65536) blocks = 65536;
+  return launch(map_scalar_kernel<ST, Op>, blocks, kScalarBlock, stream, io,
+                n);
 }
 
 template <class Op>

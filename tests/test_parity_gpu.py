@@ -389,6 +389,45 @@ def test_forward_16bit_full_size(dev, kind):
     torch.cuda.synchronize()
 
 
+def test_max_size_beyond_2_31_elements(dev):
+    """n = 2^31 + 123 BF16 (4 GiB per array): element indices past 2^31 use
+    the 64-bit paths; every output equals the exhaustive table entry of its
+    input pattern.  Then n = 2^31 + 3 FP32 with the scalar tail: the last
+    elements and a random sample against the oracle."""
+    n = (1 << 31) + 123
+    say(f"max size BF16 n={n}")
+    table_in = torch.from_numpy(
+        wl.all_16bit_patterns().view(np.int16)).to(dev).view(torch.bfloat16)
+    tab = torch.empty_like(table_in)
+    ta.ta_sin(table_in, tab)
+    gen = torch.Generator(device=dev).manual_seed(131)
+    raw = torch.randint(-32768, 32768, (n,), device=dev, generator=gen,
+                        dtype=torch.int16)
+    x = raw.view(torch.bfloat16)
+    y = torch.empty_like(x)
+    ta.ta_sin(x, y)
+    for lo in range(0, n, 1 << 30):   # check in 1 Gi-element slices
+        hi = min(n, lo + (1 << 30))
+        idx = raw[lo:hi].long() & 0xFFFF
+        assert torch.equal(y[lo:hi].view(torch.int16),
+                           tab.view(torch.int16)[idx]), (lo, hi)
+        del idx
+    del raw, x, y
+    torch.cuda.synchronize()
+    n = (1 << 31) + 3
+    say(f"max size FP32 n={n}")
+    x = torch.rand(n, device=dev, generator=gen) * 200.0 - 100.0
+    y = torch.empty_like(x)
+    ta.ta_sin(x, y)
+    torch.cuda.synchronize()
+    sample = np.concatenate([np.arange(n - 4096, n),
+                             np.random.default_rng(5).integers(0, n, 1 << 16)])
+    it = torch.from_numpy(sample).to(dev)
+    xs, ys = host(x[it]), host(y[it])
+    check_f32("max-size:sin", xs, ys, oracle.forward(xs.astype(np.float64))["sin"])
+    del x, y
+
+
 # ---------------------------------------------------------------------------
 # Taylor baseline
 # ---------------------------------------------------------------------------
