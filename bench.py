@@ -162,6 +162,14 @@ def main():
             "algorithmic_bytes_per_launch": alg_bytes,
         },
     }
+    valu = sq_per_elem().get("sincos_tan_f32")
+    if valu:
+        lane = valu * n / (kernel_ms * 1e-3)
+        out["roofline"]["valu_issue"] = {
+            "valu_per_elem": valu, "achieved": round(lane / 1e12, 2),
+            "peak": round(VALU_PEAK / 1e12, 2),
+            "unit": "1e12 VALU lane-instructions/s",
+            "frac": round(lane / VALU_PEAK, 3)}
     host_wall_ms = wall / args.steps
     out["timing_note"] = {"host_wall_ms_per_step": round(host_wall_ms, 4)}
 
@@ -325,6 +333,97 @@ def extras(args, torch, ta, dev):
         res["fused_fwdbwd"]["gbs_algorithmic"] / HBM_PEAK_GBS, 4)
     res["workload"] = ("ta_sin_fwdbwd, [128, 8192, 512] FP32, x ~ N(0, 100), "
                        "g ~ N(0, 1)")
+    del x, g, y, gx
+    res.update(other_workloads(args, torch, ta, dev))
+    return res
+
+
+def sq_per_elem():
+    """VALU instructions per element from the committed SQ summary (None
+    when it was taken on other kernel sources)."""
+    path = os.path.join(ROOT, "profiles", "ta_kernels_f32_bf16_sq_instructions.txt")
+    if not os.path.exists(path):
+        return {}
+    out, sha = {}, None
+    with open(path) as f:
+        for line in f:
+            if line.startswith("source_sha:"):
+                sha = line.split(":", 1)[1].strip()
+            if "_SQ_INSTS_VALU:" in line and "per_elem" in line:
+                key = line.split("_SQ_INSTS_VALU:")[0]
+                out[key] = float(line.rsplit("per_elem", 1)[1])
+    return out if sha == source_hash() else {}
+
+
+def other_workloads(args, torch, ta, dev):
+    """The remaining workload shapes, each timed with HIP events:
+    2^29 FP16 / BF16 U[-pi, pi] (fused sin+cos+tan and sin), 2^26 FP32 with
+    |x| = 10^U[0,6], and the [64, 4096, 256] activation (FP32 and BF16)."""
+    res = {}
+    steps = max(5, args.steps // 2)
+    valu = sq_per_elem()
+    gen = torch.Generator(device=dev).manual_seed(2024873)
+
+    def timed(fn):
+        per, total, _ = time_launches(fn, steps, 3, torch)
+        return total / steps
+
+    for tdt, tag in ((torch.bfloat16, "bf16"), (torch.float16, "f16")):
+        n = 1 << 29
+        x = (torch.rand(n, device=dev, generator=gen, dtype=torch.float64)
+             * (2 * math.pi) - math.pi).to(tdt)
+        a, b, c = (torch.empty_like(x) for _ in range(3))
+        log(f"timing 2^29 {tag}")
+        ms3 = timed(lambda: ta.ta_sincos(x, a, b, c))
+        ms1 = timed(lambda: ta.ta_sin(x, a))
+        entry = {
+            "sincos_tan": {"gelem_s": round(n / (ms3 * 1e-3) / 1e9, 1),
+                           "gbs_algorithmic": round(8 * n / (ms3 * 1e-3) / 1e9, 1)},
+            "sin": {"gelem_s": round(n / (ms1 * 1e-3) / 1e9, 1),
+                    "gbs_algorithmic": round(4 * n / (ms1 * 1e-3) / 1e9, 1)}}
+        for key, kind, ms in (("sincos_tan", "sincos_tan_bf16", ms3),
+                              ("sin", "sin_bf16", ms1)):
+            if tag == "bf16" and kind in valu:
+                lane_instr = valu[kind] * n / (ms * 1e-3)
+                entry[key]["roofline_alu"] = {
+                    "bound": "alu", "achieved": round(lane_instr / 1e12, 2),
+                    "peak": round(VALU_PEAK / 1e12, 2),
+                    "unit": "1e12 VALU lane-instructions/s",
+                    "frac": round(lane_instr / VALU_PEAK, 3),
+                    "valu_per_elem": valu[kind]}
+        res[f"{tag}_2p29_uniform_pi"] = entry
+        del x, a, b, c
+
+    n = 1 << 26
+    import numpy as np
+    from paper_2502_10831_amd import workloads as wl
+    x = torch.from_numpy(wl.log_magnitude(n)).to(dev)
+    a, b, c = (torch.empty_like(x) for _ in range(3))
+    log("timing 2^26 log-magnitude")
+    ms = timed(lambda: ta.ta_sincos(x, a, b, c))
+    res["f32_2p26_log_magnitude"] = {
+        "sincos_tan_gelem_s": round(n / (ms * 1e-3) / 1e9, 1),
+        "gbs_algorithmic": round(16 * n / (ms * 1e-3) / 1e9, 1),
+        "elements_on_bit_table_reduction": int((x.abs() >= 2.0 ** 29).sum())}
+    del x, a, b, c
+
+    shape = (64, 4096, 256)
+    n = 64 * 4096 * 256
+    xf = torch.randn(n, device=dev, generator=gen) * 3.0
+    gf = torch.randn(n, device=dev, generator=gen)
+    for tdt, tag, es in ((torch.float32, "f32", 4), (torch.bfloat16, "bf16", 2)):
+        x, g = xf.to(tdt), gf.to(tdt)
+        y, gx = torch.empty_like(x), torch.empty_like(x)
+        log(f"timing activation {shape} {tag}")
+        msf = timed(lambda: ta.ta_sin(x, y))
+        msb = timed(lambda: ta.ta_sin_bwd(x, g, gx))
+        msfb = timed(lambda: ta.ta_sin_fwdbwd(x, g, y, gx))
+        res[f"activation_64x4096x256_{tag}"] = {
+            "fwd_gelem_s": round(n / (msf * 1e-3) / 1e9, 1),
+            "bwd_gelem_s": round(n / (msb * 1e-3) / 1e9, 1),
+            "fwdbwd_gelem_s": round(n / (msfb * 1e-3) / 1e9, 1),
+            "fwdbwd_gbs_algorithmic": round(4 * es * n / (msfb * 1e-3) / 1e9, 1)}
+        del x, g, y, gx
     return res
 
 
