@@ -511,24 +511,29 @@ def summarize(a):
     mode = a[0]
     if mode == "trace":
         directory, out, cmd = a[1], a[2], " ".join(a[3:])
-        rows = _csv_rows(directory, "kernel_stats.csv")
-        lines = [f"# rocprofv3 kernel statistics (kernel-trace --stats)",
-                 f"# command: {cmd}", f"source_sha: {source_hash()}"]
-        for r in rows:
-            key = _which(r.get("Name", ""))
-            # only the kernels the bench launches at one fixed size
-            if key not in ("sincos_tan_f32", "sin_fwdbwd_f32"):
-                continue
-            avg_ns = float(r["AverageNs"])
-            lines.append(f"{key}: calls {r['Calls']} average_ns {avg_ns:.0f} "
-                         f"min_ns {float(r['MinNs']):.0f} "
-                         f"max_ns {float(r['MaxNs']):.0f}")
-            if key == "sincos_tan_f32":
-                lines.append(f"sincos_tan_f32_algorithmic_GBs: "
-                             f"{16 * (1 << 28) / avg_ns:.1f}")
-            if key == "sin_fwdbwd_f32":
-                lines.append(f"sin_fwdbwd_f32_algorithmic_GBs: "
-                             f"{16 * 128 * 8192 * 512 / avg_ns:.1f}")
+        # per-dispatch records: the bench also launches these kernels at other
+        # sizes, so keep the dispatches of the headline shapes (grid = one
+        # thread per 16-byte FP32 vector of the workload)
+        grids = {"sincos_tan_f32": (1 << 28) // 4,
+                 "sin_fwdbwd_f32": 128 * 8192 * 512 // 4}
+        algo = {"sincos_tan_f32": 16 * (1 << 28),
+                "sin_fwdbwd_f32": 16 * 128 * 8192 * 512}
+        durs = {}
+        for r in _csv_rows(directory, "kernel_trace.csv"):
+            key = _which(r.get("Kernel_Name", ""))
+            if key in grids and int(r["Grid_Size_X"]) == grids[key]:
+                durs.setdefault(key, []).append(
+                    int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+        lines = [f"# rocprofv3 kernel trace (kernel-trace --stats), dispatches "
+                 f"of the headline shapes", f"# command: {cmd}",
+                 f"source_sha: {source_hash()}"]
+        for key, d in sorted(durs.items(), reverse=True):
+            d.sort()
+            avg_ns = sum(d) / len(d)
+            lines.append(f"{key}: grid {grids[key]} calls {len(d)} "
+                         f"average_ns {avg_ns:.0f} median_ns {d[len(d) // 2]} "
+                         f"min_ns {d[0]} max_ns {d[-1]}")
+            lines.append(f"{key}_algorithmic_GBs: {algo[key] / avg_ns:.1f}")
         _write(out, lines)
     elif mode == "pmc":
         fetch_dir, write_dir, out, cmd = a[1], a[2], a[3], " ".join(a[4:])

@@ -26,30 +26,33 @@ struct F32 {
   static __device__ float load(raw v) { return __uint_as_float(v); }
   static __device__ raw store(float f) { return __float_as_uint(f); }
 };
-// 16-bit formats also round pairs with one v_cvt_pk_{f16,bf16}_f32.
+// 16-bit formats also round pairs: a <2 x float> -> <2 x half|bfloat>
+// conversion is one v_cvt_pk_{f16,bf16}_f32.
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 struct F16 {
   using raw = uint16_t;
   static __device__ float load(raw v) {
-    return __half2float(__ushort_as_half(v));
+    return float(__builtin_bit_cast(_Float16, v));
   }
   static __device__ raw store(float f) {
-    return __half_as_ushort(__float2half_rn(f));
+    return __builtin_bit_cast(raw, _Float16(f));
   }
   static __device__ uint32_t store2(float lo, float hi) {
-    const __half2 h = __float22half2_rn(make_float2(lo, hi));
-    return *reinterpret_cast<const uint32_t *>(&h);
+    const f32x2 v = {lo, hi};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, f16x2));
   }
 };
 struct BF16 {
   using raw = uint16_t;
   static __device__ float load(raw v) { return __uint_as_float(uint32_t(v) << 16); }
   static __device__ raw store(float f) {
-    const __hip_bfloat16 b = __float2bfloat16(f);
-    return *reinterpret_cast<const raw *>(&b);
+    return __builtin_bit_cast(raw, __bf16(f));
   }
   static __device__ uint32_t store2(float lo, float hi) {
-    const __hip_bfloat162 b = __float22bfloat162_rn(make_float2(lo, hi));
-    return *reinterpret_cast<const uint32_t *>(&b);
+    const f32x2 v = {lo, hi};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
   }
 };
 
@@ -71,11 +74,11 @@ struct FwdOp {
     int o = 0;
     if constexpr ((MASK & (kSin | kCos)) != 0) {
       const float y = rsqrt_refined(v.q);
-      if constexpr (MASK & kSin) out[o++] = set_sign(v.n * y, sin_mask(f));
-      if constexpr (MASK & kCos) out[o++] = set_sign(v.d * y, cos_mask(f));
+      if constexpr (MASK & kSin) out[o++] = flip_sign(v.n * y, sin_mask(f));
+      if constexpr (MASK & kCos) out[o++] = flip_sign(v.d * y, cos_mask(f));
     }
     if constexpr (MASK & kTan) {
-      float t = set_sign(div_refined(v.n, v.d), tan_mask(f));
+      float t = flip_sign(div_refined(v.n, v.d), tan_mask(f));
       if constexpr (GUARD) {
         // Section 3 proposed_tan: +inf within 1e-3 of pi/2, before the sign.
         if ((f.q & 1u) && f.abs_r() < 1e-3) t = __builtin_inff();
@@ -120,12 +123,12 @@ struct BwdOp {
     if constexpr (WHICH == kTan) {
       const float r = rcp_refined(v.d);
       const float dt = kdet * r * r;
-      if constexpr (WITH_Y) out[0] = set_sign(div_refined(v.n, v.d), tan_mask(f));
+      if constexpr (WITH_Y) out[0] = flip_sign(div_refined(v.n, v.d), tan_mask(f));
       out[WITH_Y ? 1 : 0] = in[1] * dt;
     } else {
       const float y = rsqrt_refined(v.q);
-      const float s = set_sign(v.n * y, sin_mask(f));
-      const float c = set_sign(v.d * y, cos_mask(f));
+      const float s = flip_sign(v.n * y, sin_mask(f));
+      const float c = flip_sign(v.d * y, cos_mask(f));
       const float omega = kdet * y * y;
       if constexpr (WHICH == kSin) {
         if constexpr (WITH_Y) out[0] = s;
@@ -151,9 +154,9 @@ struct SinCosBwdOp {
     const float y = rsqrt_refined(v.q);
     const float omega = tb.kdet[f.row] * y * y;
     float acc = 0.0f;
-    if constexpr (HAS_GS) acc = in[1] * set_sign(v.d * y, cos_mask(f));
+    if constexpr (HAS_GS) acc = in[1] * flip_sign(v.d * y, cos_mask(f));
     if constexpr (HAS_GC)
-      acc = __builtin_fmaf(-in[HAS_GS ? 2 : 1], set_sign(v.n * y, sin_mask(f)),
+      acc = __builtin_fmaf(-in[HAS_GS ? 2 : 1], flip_sign(v.n * y, sin_mask(f)),
                            acc);
     out[0] = omega * acc;
   }

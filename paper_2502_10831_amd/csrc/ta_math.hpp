@@ -56,10 +56,7 @@ constexpr int kD[6] = {632, 657, 541, 1252, 910, 990};
 // and with t = a (the complement) N = (90 a_k + b_k) - a_k t and
 // D = (90 c_k + d_k) - c_k t.
 struct PieceRow {
-  // N = iN + sN a, D = iD + sD a with a = |r| in radians: the integer slopes
-  // times 180/pi, rounded once in FP64 (a 2^-53 relative change of the
-  // slope; the degree conversion of a is folded into it)
-  double iN, sN, iD, sD;
+  double iN, sN, iD, sD;  // N = iN + sN t, D = iD + sD t (t in degrees)
 };
 
 __host__ __device__ constexpr int piece_of_row(int idx) {
@@ -68,12 +65,10 @@ __host__ __device__ constexpr int piece_of_row(int idx) {
 
 __host__ __device__ constexpr PieceRow piece_row(int idx) {
   const int k = piece_of_row(idx);
-  return idx < 3 ? PieceRow{double(kB[k]), double(kA[k]) * kDegPerRad,
-                            double(kD[k]), double(kC[k]) * kDegPerRad}
-                 : PieceRow{double(90 * kA[k] + kB[k]),
-                            double(-kA[k]) * kDegPerRad,
-                            double(90 * kC[k] + kD[k]),
-                            double(-kC[k]) * kDegPerRad};
+  return idx < 3 ? PieceRow{double(kB[k]), double(kA[k]), double(kD[k]),
+                            double(kC[k])}
+                 : PieceRow{double(90 * kA[k] + kB[k]), double(-kA[k]),
+                            double(90 * kC[k] + kD[k]), double(-kC[k])};
 }
 
 // (180/pi) * (a_k d_k - b_k c_k): d(tan piece)/d rho = this / D^2, and the
@@ -180,14 +175,13 @@ __device__ inline void reduce(float x, double &r, uint32_t &q) {
 
 // Folded element: everything the later stages need.
 constexpr double kPi12 = 0x1.0c152382d7366p-2;  // RN(pi/12)
-constexpr double kPi6 = 0x1.0c152382d7366p-1;   // RN(pi/6)
 
 struct Folded {
   double r;       // reduced argument, |r| <= pi/4 (use abs_r())
+  double t;       // |r| in degrees, [0, 45]
   uint32_t q;     // quadrant, low bits
   uint32_t hr;    // high word of r: bit 31 = sign of r
   uint32_t row;   // LDS table slot j + 4*(q & 1)
-  // |r|, written at each use so that it folds into a source modifier
   __device__ double abs_r() const { return __builtin_fabs(r); }
 };
 
@@ -195,33 +189,30 @@ __device__ inline Folded fold(float x) {
   Folded f;
   reduce(x, f.r, f.q);
   f.hr = uint32_t(__double2hiint(f.r));
+  f.t = f.abs_r() * kDegPerRad;  // the abs folds into the multiply
   // j = 15-degree slot of |r|; the family (q & 1) selects slots 4..6
-  const uint32_t j =
-      f.abs_r() >= kPi6 ? 2u : (f.abs_r() >= kPi12 ? 1u : 0u);
+  const uint32_t j = f.t >= 30.0 ? 2u : (f.t >= 15.0 ? 1u : 0u);
   f.row = ((f.q << 2) & 4u) | j;
   return f;
 }
 
-// Output signs as bit 31 of a word (other bits are don't-care), from the
-// quadrant q and the sign of r, sr:
-//   sin: sr ^ q1 for even q, q1 for odd q;
-//   cos: q0 ^ q1 for even q, q0 ^ q1 ^ sr for odd q;
-//   tan: sr ^ q0.
-__device__ inline uint32_t odd_mask(const Folded &f) { return 0u - (f.q & 1u); }
+// Output signs as bit 31 of a word (other bits are don't-care).  With
+// a = sign of r, b = q0, c = q1 (all at bit 31), each is one 3-input
+// boolean function (one v_bitop3_b32):
+//   sin: c ^ (a & ~b)   (q1 ^ sr for even q, q1 for odd q)
+//   cos: c ^ (b & ~a)   (q1 for even q, q1 ^ 1 ^ sr for odd q)
+//   tan: a ^ b
 __device__ inline uint32_t sin_mask(const Folded &f) {
-  return (f.hr & ~odd_mask(f)) ^ (f.q << 30);
+  return (f.q << 30) ^ (f.hr & ~(f.q << 31));
 }
 __device__ inline uint32_t cos_mask(const Folded &f) {
-  return (f.hr & odd_mask(f)) ^ (f.q << 30) ^ (f.q << 31);
+  return (f.q << 30) ^ ((f.q << 31) & ~f.hr);
 }
 __device__ inline uint32_t tan_mask(const Folded &f) { return f.hr ^ (f.q << 31); }
 
-// Sets the sign of a non-negative value v to bit 31 of m (one v_bfi_b32).
-__device__ inline float set_sign(float v, uint32_t m) {
-  return __uint_as_float((__float_as_uint(v) & 0x7fffffffu) |
-                         (m & 0x80000000u));
-}
-// Flips the sign of v by bit 31 of m.
+// Applies the sign in bit 31 of m to v: v ^ (m & 0x80000000).  The unsigned
+// values of the method (N y, D y, N/D with N, D >= 0) and of the Taylor
+// series on [0, pi/2] are non-negative, so this sets the sign.
 __device__ inline float flip_sign(float v, uint32_t m) {
   return __uint_as_float(__float_as_uint(v) ^ (m & 0x80000000u));
 }
@@ -235,8 +226,8 @@ struct Forms {
 
 __device__ inline Forms forms(const Folded &f, const Tables &tb) {
   const PieceRow c = tb.row[f.row];
-  const double nd = __builtin_fma(c.sN, f.abs_r(), c.iN);
-  const double dd = __builtin_fma(c.sD, f.abs_r(), c.iD);
+  const double nd = __builtin_fma(c.sN, f.t, c.iN);
+  const double dd = __builtin_fma(c.sD, f.t, c.iD);
   const double qd = __builtin_fma(nd, nd, dd * dd);
   return Forms{float(nd), float(dd), float(qd)};
 }

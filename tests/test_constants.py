@@ -34,7 +34,6 @@ def test_reduction_constants(text):
     assert _const(text, "kDegPerRad") == float(180 / pi)
     assert _const(text, "kRoundMagic") == 1.5 * 2.0 ** 52
     assert _const(text, "kPi12") == float(pi / 12)
-    assert _const(text, "kPi6") == float(pi / 6)
 
 
 def test_two_over_pi_bits(text):
