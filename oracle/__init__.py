@@ -6,7 +6,9 @@ and by the benchmark's ``cpu_baseline`` leg, never by the GPU package.  The C
 source (``ta_oracle.c``) shares nothing with the HIP kernels.
 
 Functions take float64 numpy arrays (FP32 or 16-bit inputs convert to float64
-exactly) and return float64 arrays.  See ``ta_oracle.c`` for the readings of
+exactly) and return float64 arrays; the ``*_ld`` forms evaluate the same
+definitions in x87 long double (64-bit significand) and return np.longdouble
+arrays, for checking FP64 outputs.  See ``ta_oracle.c`` for the readings of
 the paper that the oracle takes where the paper is silent.
 """
 from __future__ import annotations
@@ -60,6 +62,11 @@ def _load():
                                 D, D]
     lib.ta_or_piece_scs.argtypes = [ctypes.c_int, ctypes.c_double,
                                     ctypes.c_double, D, D, D]
+    L = ctypes.POINTER(ctypes.c_longdouble)
+    lib.ta_or_map_ld.argtypes = [D, i64, L, L, L, ctypes.c_uint, ctypes.c_int]
+    lib.ta_or_map_ld.restype = ctypes.c_int
+    lib.ta_or_fold_map_ld.argtypes = [D, i64, L, L, I32]
+    lib.ta_or_grad_map_ld.argtypes = [D, i64, ctypes.c_int, L, L, L]
     lib.ta_or_segment.argtypes = [ctypes.c_double]
     lib.ta_or_segment.restype = ctypes.c_int
     _lib = lib
@@ -182,4 +189,58 @@ def paper(x, divisor: float = np.pi / 12, flags: int = 0):
     out = {k: np.empty(n) for k in ("sin", "cos", "tan")}
     lib.ta_or_paper_map(_dp(x), n, float(divisor), int(flags),
                         _dp(out["sin"]), _dp(out["cos"]), _dp(out["tan"]))
+    return out
+
+
+# ---- extended precision (long double) forms, for checking FP64 outputs ----
+def _lp(a):
+    if a is None:
+        return ctypes.POINTER(ctypes.c_longdouble)()
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_longdouble))
+
+
+def _check_longdouble():
+    if np.finfo(np.longdouble).nmant < 63:
+        raise RuntimeError("the extended-precision oracle needs an 80-bit "
+                           "long double")
+
+
+def forward_ld(x, flags: int = 0, shift: int = 0,
+               want=("sin", "cos", "tan")):
+    """The method in long double (64-bit significand) on double inputs:
+    dict name -> np.longdouble array.  shift evaluates piece k + shift
+    (clamped) instead of the piece rho falls in."""
+    _check_longdouble()
+    lib = _load()
+    x = _x(x)
+    n = x.size
+    out = {k: np.empty(n, np.longdouble) for k in want}
+    lib.ta_or_map_ld(_dp(x), n, _lp(out.get("sin")), _lp(out.get("cos")),
+                     _lp(out.get("tan")), flags, int(shift))
+    return out
+
+
+def fold_ld(x):
+    """Fold angle rho, complement v (np.longdouble) and piece index k."""
+    _check_longdouble()
+    lib = _load()
+    x = _x(x)
+    n = x.size
+    rho = np.empty(n, np.longdouble)
+    v = np.empty(n, np.longdouble)
+    k = np.empty(n, np.int32)
+    lib.ta_or_fold_map_ld(_dp(x), n, _lp(rho), _lp(v),
+                          k.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    return rho, v, k
+
+
+def grad_ld(x, shift: int = 0):
+    """d/dx of the method's sin, cos and tan in long double."""
+    _check_longdouble()
+    lib = _load()
+    x = _x(x)
+    n = x.size
+    out = {k: np.empty(n, np.longdouble) for k in ("sin", "cos", "tan")}
+    lib.ta_or_grad_map_ld(_dp(x), n, int(shift), _lp(out["sin"]),
+                          _lp(out["cos"]), _lp(out["tan"]))
     return out

@@ -385,3 +385,146 @@ void ta_or_paper_map(const double *x, int64_t n, double divisor,
     if (yt) yt[i] = t;
   }
 }
+
+/* ---- the method in extended precision ------------------------------------
+ * The same definitions (readings R1-R7) evaluated in x87 long double (64-bit
+ * significand) from double inputs, to check FP64 outputs: each result here is
+ * within a few units of 2^-64 of the exact value of the formulas at x, about
+ * 2^-10 of an FP64 ulp.  glibc's sinl/cosl reduce any double argument
+ * accurately, so the fold keeps full relative precision near the zeros of
+ * sin and cos.  `shift` evaluates the piece k + shift (clamped to 0..5)
+ * instead of the piece k that rho falls in: a checker uses shift = -1 and +1
+ * for inputs whose rho is within rounding distance of a piece boundary. */
+static long double or_kl(void) { return 180.0L / acosl(-1.0L); }
+
+void ta_or_fold_ld(double x, long double *rho, long double *v, int *neg_s,
+                   int *neg_c) {
+  long double s = sinl((long double)x), c = cosl((long double)x);
+  *rho = atan2l(fabsl(s), fabsl(c));
+  *v = atan2l(fabsl(c), fabsl(s));
+  *neg_s = signbit(s) ? 1 : 0;
+  *neg_c = signbit(c) ? 1 : 0;
+}
+
+static int or_segment_ld(long double rho) {
+  int k = (int)floorl(rho / (acosl(-1.0L) / 12.0L));
+  if (k > 5) k = 5;
+  if (k < 0) k = 0;
+  return k;
+}
+
+static void or_piece_ld(int k, long double rho, long double v,
+                        long double *num, long double *den) {
+  long double K = or_kl();
+  if (k <= 2) {
+    long double t = rho * K;
+    *num = (long double)OR_A[k] * t + (long double)OR_B[k];
+    *den = (long double)OR_C[k] * t + (long double)OR_D[k];
+  } else {
+    long double w = v * K;
+    *num = (90.0L * OR_A[k] + OR_B[k]) - (long double)OR_A[k] * w;
+    *den = (90.0L * OR_C[k] + OR_D[k]) - (long double)OR_C[k] * w;
+  }
+}
+
+static void or_eval_ld(double x, unsigned flags, int shift, long double *ys,
+                       long double *yc, long double *yt) {
+  if (isnan(x) || isinf(x)) {
+    *ys = *yc = *yt = NAN;
+    return;
+  }
+  long double rho, v;
+  int ns, nc;
+  ta_or_fold_ld(x, &rho, &v, &ns, &nc);
+  int k = or_segment_ld(rho) + shift;
+  if (k < 0) k = 0;
+  if (k > 5) k = 5;
+  long double n, d;
+  or_piece_ld(k, rho, v, &n, &d);
+  long double h = sqrtl(n * n + d * d);
+  long double s = n / h, c = d / h, t = n / d;
+  *ys = ns ? -s : s;
+  *yc = nc ? -c : c;
+  if ((flags & TA_OR_TAN_GUARD) && v < 1e-3L) {
+    *yt = INFINITY;
+  } else {
+    *yt = (ns != nc) ? -t : t;
+  }
+}
+
+int ta_or_map_ld(const double *x, int64_t n, long double *ys, long double *yc,
+                 long double *yt, unsigned flags, int shift) {
+  int used = 1;
+#pragma omp parallel
+  {
+#ifdef _OPENMP
+#pragma omp single
+    used = omp_get_num_threads();
+#endif
+#pragma omp for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+      long double s, c, t;
+      or_eval_ld(x[i], flags, shift, &s, &c, &t);
+      if (ys) ys[i] = s;
+      if (yc) yc[i] = c;
+      if (yt) yt[i] = t;
+    }
+  }
+  return used;
+}
+
+/* Fold angle, complement (both long double) and piece index per element. */
+void ta_or_fold_map_ld(const double *x, int64_t n, long double *rho,
+                       long double *v, int32_t *k) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    long double r = NAN, w = NAN;
+    int a, b;
+    if (!(isnan(x[i]) || isinf(x[i]))) ta_or_fold_ld(x[i], &r, &w, &a, &b);
+    rho[i] = r;
+    v[i] = w;
+    k[i] = isnan(r) ? -1 : or_segment_ld(r);
+  }
+}
+
+/* Derivative of the selected piece (as ta_or_grad_map) in long double;
+ * `shift` as in ta_or_map_ld. */
+static void or_grad_eval_ld(double x, int shift, long double *gs,
+                            long double *gc, long double *gt) {
+  if (isnan(x) || isinf(x)) {
+    *gs = *gc = *gt = NAN;
+    return;
+  }
+  long double rho, v;
+  int ns, nc;
+  ta_or_fold_ld(x, &rho, &v, &ns, &nc);
+  int k = or_segment_ld(rho) + shift;
+  if (k < 0) k = 0;
+  if (k > 5) k = 5;
+  long double n, d;
+  or_piece_ld(k, rho, v, &n, &d);
+  long double det = (long double)OR_A[k] * OR_D[k] -
+                    (long double)OR_B[k] * OR_C[k];
+  long double q = n * n + d * d;
+  long double Kdet = or_kl() * det;
+  long double dS = Kdet * d / (q * sqrtl(q));
+  long double dC = -Kdet * n / (q * sqrtl(q));
+  long double dT = Kdet / (d * d);
+  long double sig_s = ns ? -1.0L : 1.0L, sig_c = nc ? -1.0L : 1.0L;
+  long double drho_dx = sig_s * sig_c;
+  *gs = sig_s * dS * drho_dx;
+  *gc = sig_c * dC * drho_dx;
+  *gt = sig_s * sig_c * dT * drho_dx;
+}
+
+void ta_or_grad_map_ld(const double *x, int64_t n, int shift, long double *gs,
+                       long double *gc, long double *gt) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    long double a, b, c;
+    or_grad_eval_ld(x[i], shift, &a, &b, &c);
+    if (gs) gs[i] = a;
+    if (gc) gc[i] = b;
+    if (gt) gt[i] = c;
+  }
+}
