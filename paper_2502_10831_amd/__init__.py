@@ -36,11 +36,11 @@ __all__ = [
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = os.path.join(_HERE, "libta.so")
 
-TA_F32, TA_F16, TA_BF16 = 0, 1, 2
+TA_F32, TA_F16, TA_BF16, TA_F64 = 0, 1, 2, 3
 TA_FLAG_TAN_GUARD = 1
 TA_FLAG_LITERAL_DIVISOR = 2
 _DTYPE_CODE = {torch.float32: TA_F32, torch.float16: TA_F16,
-               torch.bfloat16: TA_BF16}
+               torch.bfloat16: TA_BF16, torch.float64: TA_F64}
 
 _lib = None
 

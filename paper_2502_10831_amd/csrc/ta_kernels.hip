@@ -18,21 +18,53 @@
 namespace ta {
 
 // ---------------------------------------------------------------------------
-// Storage formats.  Loads widen exactly to FP32; stores round to nearest
-// even.
+// Storage formats.  `val` is the arithmetic type of the element functors:
+// FP32 for the FP32 and 16-bit formats (loads widen exactly, stores round
+// to nearest even), FP64 for FP64.  unpack/pack convert one 16-byte access.
 // ---------------------------------------------------------------------------
-struct F32 {
-  using raw = uint32_t;
-  static __device__ float load(raw v) { return __uint_as_float(v); }
-  static __device__ raw store(float f) { return __float_as_uint(f); }
-};
-// 16-bit formats also round pairs: a <2 x float> -> <2 x half|bfloat>
-// conversion is one v_cvt_pk_{f16,bf16}_f32.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
-struct F16 {
+
+struct F32 {
+  using raw = uint32_t;
+  using val = float;
+  static constexpr int kVec = 4;
+  static __device__ val load(raw v) { return __uint_as_float(v); }
+  static __device__ raw store(val f) { return __float_as_uint(f); }
+  static __device__ void unpack(const u32x4 &w, val *v) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v[e] = __uint_as_float(w[e]);
+  }
+  static __device__ u32x4 pack(const val *v) {
+    u32x4 w;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) w[e] = __float_as_uint(v[e]);
+    return w;
+  }
+};
+
+// 16-bit formats round pairs: a <2 x float> -> <2 x half|bfloat>
+// conversion is one v_cvt_pk_{f16,bf16}_f32.
+template <class Derived>
+struct Half16 {
   using raw = uint16_t;
+  using val = float;
+  static constexpr int kVec = 8;
+  static __device__ void unpack(const u32x4 &w, val *v) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+      v[e] = Derived::load(uint16_t(w[e >> 1] >> (16 * (e & 1))));
+  }
+  static __device__ u32x4 pack(const val *v) {
+    u32x4 w;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) w[j] = Derived::store2(v[2 * j], v[2 * j + 1]);
+    return w;
+  }
+};
+struct F16 : Half16<F16> {
   static __device__ float load(raw v) {
     return float(__builtin_bit_cast(_Float16, v));
   }
@@ -44,8 +76,7 @@ struct F16 {
     return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, f16x2));
   }
 };
-struct BF16 {
-  using raw = uint16_t;
+struct BF16 : Half16<BF16> {
   static __device__ float load(raw v) { return __uint_as_float(uint32_t(v) << 16); }
   static __device__ raw store(float f) {
     return __builtin_bit_cast(raw, __bf16(f));
@@ -53,6 +84,29 @@ struct BF16 {
   static __device__ uint32_t store2(float lo, float hi) {
     const f32x2 v = {lo, hi};
     return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
+  }
+};
+
+struct F64 {
+  using raw = uint64_t;
+  using val = double;
+  static constexpr int kVec = 2;
+  static __device__ val load(raw v) { return __longlong_as_double(int64_t(v)); }
+  static __device__ raw store(val f) { return raw(__double_as_longlong(f)); }
+  static __device__ void unpack(const u32x4 &w, val *v) {
+#pragma unroll
+    for (int e = 0; e < 2; ++e)
+      v[e] = load((uint64_t(w[2 * e + 1]) << 32) | w[2 * e]);
+  }
+  static __device__ u32x4 pack(const val *v) {
+    u32x4 w;
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const raw b = store(v[e]);
+      w[2 * e] = uint32_t(b);
+      w[2 * e + 1] = uint32_t(b >> 32);
+    }
+    return w;
   }
 };
 
@@ -86,6 +140,24 @@ struct FwdOp {
       out[o++] = t;
     }
   }
+  __device__ static void apply(const double *in, double *out, const Table &tb,
+                               uint32_t) {
+    const Folded64 f = fold64(in[0]);
+    const Forms64 v = forms64(f, tb);
+    int o = 0;
+    if constexpr ((MASK & (kSin | kCos)) != 0) {
+      const double y = rsqrt64_refined(v.q);
+      if constexpr (MASK & kSin) out[o++] = flip_sign(v.n * y, sin_mask(f));
+      if constexpr (MASK & kCos) out[o++] = flip_sign(v.d * y, cos_mask(f));
+    }
+    if constexpr (MASK & kTan) {
+      double t = flip_sign(div64_refined(v.n, v.d), tan_mask(f));
+      if constexpr (GUARD) {
+        if ((f.q & 1u) && f.abs_r() < 1e-3) t = __builtin_inf();
+      }
+      out[o++] = t;
+    }
+  }
 };
 
 template <int MASK, int TERMS>
@@ -97,6 +169,17 @@ struct TaylorOp {
                                   uint32_t) {
     const Folded f = fold(in[0]);
     const float rho = fold_rho(f);
+    if constexpr (MASK == kSin)
+      out[0] = flip_sign(taylor_sin_unsigned<TERMS>(rho), sin_mask(f));
+    if constexpr (MASK == kCos)
+      out[0] = flip_sign(taylor_cos_unsigned<TERMS>(rho), cos_mask(f));
+    if constexpr (MASK == kTan)
+      out[0] = flip_sign(taylor_tan_unsigned<TERMS>(rho), tan_mask(f));
+  }
+  __device__ static void apply(const double *in, double *out, const Table &,
+                               uint32_t) {
+    const Folded64 f = fold64(in[0]);
+    const double rho = fold_rho64(f);
     if constexpr (MASK == kSin)
       out[0] = flip_sign(taylor_sin_unsigned<TERMS>(rho), sin_mask(f));
     if constexpr (MASK == kCos)
@@ -139,6 +222,33 @@ struct BwdOp {
       }
     }
   }
+  __device__ static void apply(const double *in, double *out, const Table &tb,
+                               uint32_t) {
+    const Folded64 f = fold64(in[0]);
+    const Forms64 v = forms64(f, tb);
+    const double kdet = tb.kdet64[f.row];
+    if constexpr (WHICH == kTan) {
+      const double r = rcp64_refined(v.d);
+      const double dt = kdet * r * r;
+      if constexpr (WITH_Y)
+        out[0] = flip_sign(__builtin_fma(__builtin_fma(-v.d, v.n * r, v.n), r,
+                                         v.n * r),
+                           tan_mask(f));
+      out[WITH_Y ? 1 : 0] = in[1] * dt;
+    } else {
+      const double y = rsqrt64_refined(v.q);
+      const double s = flip_sign(v.n * y, sin_mask(f));
+      const double c = flip_sign(v.d * y, cos_mask(f));
+      const double omega = kdet * y * y;
+      if constexpr (WHICH == kSin) {
+        if constexpr (WITH_Y) out[0] = s;
+        out[WITH_Y ? 1 : 0] = in[1] * (omega * c);
+      } else {
+        if constexpr (WITH_Y) out[0] = c;
+        out[WITH_Y ? 1 : 0] = -(in[1] * (omega * s));
+      }
+    }
+  }
 };
 
 // gx = gs * d sin_a/dx + gc * d cos_a/dx = omega (gs cos_a - gc sin_a).
@@ -158,6 +268,19 @@ struct SinCosBwdOp {
     if constexpr (HAS_GC)
       acc = __builtin_fmaf(-in[HAS_GS ? 2 : 1], flip_sign(v.n * y, sin_mask(f)),
                            acc);
+    out[0] = omega * acc;
+  }
+  __device__ static void apply(const double *in, double *out, const Table &tb,
+                               uint32_t) {
+    const Folded64 f = fold64(in[0]);
+    const Forms64 v = forms64(f, tb);
+    const double y = rsqrt64_refined(v.q);
+    const double omega = tb.kdet64[f.row] * y * y;
+    double acc = 0.0;
+    if constexpr (HAS_GS) acc = in[1] * flip_sign(v.d * y, cos_mask(f));
+    if constexpr (HAS_GC)
+      acc = __builtin_fma(-in[HAS_GS ? 2 : 1], flip_sign(v.n * y, sin_mask(f)),
+                          acc);
     out[0] = omega * acc;
   }
 };
@@ -190,6 +313,24 @@ struct PaperOp {
       out[o++] = tt;
     }
   }
+  __device__ static void apply(const double *in, double *out, const Table &tb,
+                               uint32_t flags) {
+    const Folded64 f = fold64(in[0]);
+    const double ang = fold_rho64(f);
+    const double divisor =
+        (flags & TA_FLAG_LITERAL_DIVISOR) ? kLiteralDivisor : kPi12;
+    double s, c, t;
+    paper_eval(ang, divisor, tb, s, c, t);
+    int o = 0;
+    if constexpr (MASK & kSin) out[o++] = flip_sign(s, sin_mask(f));
+    if constexpr (MASK & kCos) out[o++] = flip_sign(c, cos_mask(f));
+    if constexpr (MASK & kTan) {
+      double tt = flip_sign(t, tan_mask(f));
+      if ((flags & TA_FLAG_TAN_GUARD) && (f.q & 1u) && f.abs_r() < 1e-3)
+        tt = __builtin_inf();
+      out[o++] = tt;
+    }
+  }
 };
 
 // Comparators: the GPU's built-in functions in the same skeleton.
@@ -217,6 +358,22 @@ struct BuiltinOp {
       if constexpr (WITH_TAN) out[2] = tanf(x);
     }
   }
+  // FP64: the device library's sin/cos/tan (kind 0) or sincos + tan (kind
+  // 2); there are no FP64 hardware approximations (kind 1).
+  __device__ static void apply(const double *in, double *out, const Table &,
+                               uint32_t) {
+    const double x = in[0];
+    if constexpr (KIND == 2) {
+      double s, c;
+      sincos(x, &s, &c);
+      out[0] = s;
+      out[1] = c;
+    } else {
+      out[0] = sin(x);
+      out[1] = cos(x);
+    }
+    if constexpr (WITH_TAN) out[2] = tan(x);
+  }
 };
 
 template <int NI, int NO>
@@ -224,8 +381,8 @@ struct CopyOp {
   static constexpr int NIN = NI;
   static constexpr int NOUT = NO;
   using Table = NoTable;
-  __device__ static void apply(const float *in, float *out, const Table &,
-                                  uint32_t) {
+  template <class V>
+  __device__ static void apply(const V *in, V *out, const Table &, uint32_t) {
 #pragma unroll
     for (int j = 0; j < NO; ++j) out[j] = in[j % NI];
   }
@@ -238,11 +395,6 @@ struct IoPtrs {
   const char *in[3];
   char *out[3];
   uint32_t flags;  // runtime flag bits for the element functor
-};
-
-template <class ST>
-struct Vec {
-  static constexpr int kElems = 16 / int(sizeof(typename ST::raw));
 };
 
 // Launch shape of the vector body, per kernel category, chosen by timing on
@@ -266,15 +418,21 @@ struct Shape {
 #ifndef TA_SHAPE_TWOIN
 #define TA_SHAPE_TWOIN {128, 1, true, true}
 #endif
+#ifndef TA_SHAPE_F64
+#define TA_SHAPE_F64 {256, 2, false, true}
+#endif
+#ifndef TA_SHAPE_F64_TWOIN
+#define TA_SHAPE_F64_TWOIN {128, 2, true, true}
+#endif
 
 template <class ST, class Op>
 constexpr Shape shape_for() {
+  if (sizeof(typename ST::raw) == 8)
+    return Op::NIN >= 2 ? Shape TA_SHAPE_F64_TWOIN : Shape TA_SHAPE_F64;
   if (Op::NIN >= 2) return Shape TA_SHAPE_TWOIN;
   if (Op::NOUT >= 2 && sizeof(typename ST::raw) == 4) return Shape TA_SHAPE_MULTI;
   return Shape TA_SHAPE_SINGLE;
 }
-
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 template <bool NT>
 __device__ inline u32x4 vload(const char *base, int64_t v) {
@@ -296,7 +454,7 @@ template <class ST, class Op>
 __device__ inline void scalar_element(const IoPtrs &io, int64_t i,
                                       const typename Op::Table &tb) {
   using raw = typename ST::raw;
-  float in[Op::NIN], out[Op::NOUT];
+  typename ST::val in[Op::NIN], out[Op::NOUT];
 #pragma unroll
   for (int k = 0; k < Op::NIN; ++k)
     in[k] = ST::load(reinterpret_cast<const raw *>(io.in[k])[i]);
@@ -314,7 +472,7 @@ template <class ST, class Op, int BLOCK, int UNROLL, bool NTL, bool NTS>
 __global__ __launch_bounds__(BLOCK) void map_vec_kernel(IoPtrs io, int64_t head,
                                                         int64_t nvec, int64_t n) {
   using raw = typename ST::raw;
-  constexpr int VEC = Vec<ST>::kElems;
+  constexpr int VEC = ST::kVec;
   __shared__ typename Op::Table tb;
   if constexpr (Op::Table::kUsed) {
     Op::Table::init(tb);
@@ -342,29 +500,22 @@ __global__ __launch_bounds__(BLOCK) void map_vec_kernel(IoPtrs io, int64_t head,
   for (int u = 0; u < UNROLL; ++u) {
     const int64_t v = v0 + int64_t(u) * BLOCK;
     if (v < nvec) {
-      float res[Op::NOUT][VEC];
+      using val = typename ST::val;
+      val arg[Op::NIN][VEC], res[Op::NOUT][VEC];
+#pragma unroll
+      for (int k = 0; k < Op::NIN; ++k) ST::unpack(in_raw[u][k], arg[k]);
 #pragma unroll
       for (int e = 0; e < VEC; ++e) {
-        float in[Op::NIN], out[Op::NOUT];
+        val in[Op::NIN], out[Op::NOUT];
 #pragma unroll
-        for (int k = 0; k < Op::NIN; ++k)
-          in[k] = ST::load(reinterpret_cast<const raw *>(&in_raw[u][k])[e]);
+        for (int k = 0; k < Op::NIN; ++k) in[k] = arg[k][e];
         Op::apply(in, out, tb, io.flags);
 #pragma unroll
         for (int k = 0; k < Op::NOUT; ++k) res[k][e] = out[k];
       }
 #pragma unroll
-      for (int k = 0; k < Op::NOUT; ++k) {
-        u32x4 w;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          if constexpr (VEC == 4)
-            w[j] = ST::store(res[k][j]);
-          else
-            w[j] = ST::store2(res[k][2 * j], res[k][2 * j + 1]);
-        }
-        vstore<NTS>(out_base[k], v, w);
-      }
+      for (int k = 0; k < Op::NOUT; ++k)
+        vstore<NTS>(out_base[k], v, ST::pack(res[k]));
     }
   }
   if (blockIdx.x == 0) {
@@ -394,37 +545,42 @@ hipError_t launch(void (*kernel)(KArgs...), int64_t blocks, int threads,
 
 // Multi-frequency encoding: plane 2j holds sin_a(2^j x), plane 2j+1
 // cos_a(2^j x), j < nfreq, each plane n elements long.  One read of x, 2 nfreq
-// writes; 2^j x is exact in FP32 (it overflows to +-Inf, hence NaN, only for
-// |x| >= 2^(128-j)).  VEC_PATH: 16-byte accesses (every plane then starts
-// 16-byte aligned at element `head`), otherwise one element per lane.
+// writes; 2^j x is exact (it overflows to +-Inf, hence NaN, only for
+// |x| >= 2^(128-j) in FP32, 2^(1024-j) in FP64).  VEC_PATH: 16-byte accesses
+// (every plane then starts 16-byte aligned at element `head`), otherwise one
+// element per lane.
 constexpr int kEncodeBlock = 256;
+__device__ inline float pow2(int j, float) {
+  return __uint_as_float(uint32_t(127 + j) << 23);
+}
+__device__ inline double pow2(int j, double) {
+  return __longlong_as_double(int64_t(1023 + j) << 52);
+}
 template <class ST, bool VEC_PATH>
 __global__ __launch_bounds__(kEncodeBlock) void encode_kernel(
     const char *x, char *y, int64_t n, int nfreq, int64_t head, int64_t nvec) {
   using raw = typename ST::raw;
+  using val = typename ST::val;
   using Core = FwdOp<kSin | kCos, false>;
-  constexpr int VEC = VEC_PATH ? Vec<ST>::kElems : 1;
+  constexpr int VEC = VEC_PATH ? ST::kVec : 1;
   __shared__ Tables tb;
   Tables::init(tb);
   __syncthreads();
   const int64_t plane = n * int64_t(sizeof(raw));
   const int64_t v = int64_t(blockIdx.x) * kEncodeBlock + threadIdx.x;
   if (v < nvec) {
-    float xf[VEC];
+    val xf[VEC];
     if constexpr (VEC_PATH) {
-      const u32x4 w = vload<false>(x + head * int64_t(sizeof(raw)), v);
-#pragma unroll
-      for (int e = 0; e < VEC; ++e)
-        xf[e] = ST::load(reinterpret_cast<const raw *>(&w)[e]);
+      ST::unpack(vload<false>(x + head * int64_t(sizeof(raw)), v), xf);
     } else {
       xf[0] = ST::load(reinterpret_cast<const raw *>(x)[v]);
     }
     for (int j = 0; j < nfreq; ++j) {
-      float sv[VEC], cv[VEC];
+      val sv[VEC], cv[VEC];
 #pragma unroll
       for (int e = 0; e < VEC; ++e) {
-        const float in[1] = {xf[e] * __uint_as_float(uint32_t(127 + j) << 23)};
-        float out[2];
+        const val in[1] = {xf[e] * pow2(j, val())};
+        val out[2];
         Core::apply(in, out, tb, 0u);
         sv[e] = out[0];
         cv[e] = out[1];
@@ -432,19 +588,8 @@ __global__ __launch_bounds__(kEncodeBlock) void encode_kernel(
       char *ps = y + (2 * j) * plane;
       char *pc = ps + plane;
       if constexpr (VEC_PATH) {
-        u32x4 ws, wc;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          if constexpr (VEC == 4) {
-            ws[k] = ST::store(sv[k]);
-            wc[k] = ST::store(cv[k]);
-          } else {
-            ws[k] = ST::store2(sv[2 * k], sv[2 * k + 1]);
-            wc[k] = ST::store2(cv[2 * k], cv[2 * k + 1]);
-          }
-        }
-        vstore<true>(ps + head * int64_t(sizeof(raw)), v, ws);
-        vstore<true>(pc + head * int64_t(sizeof(raw)), v, wc);
+        vstore<true>(ps + head * int64_t(sizeof(raw)), v, ST::pack(sv));
+        vstore<true>(pc + head * int64_t(sizeof(raw)), v, ST::pack(cv));
       } else {
         reinterpret_cast<raw *>(ps)[v] = ST::store(sv[0]);
         reinterpret_cast<raw *>(pc)[v] = ST::store(cv[0]);
@@ -456,10 +601,10 @@ __global__ __launch_bounds__(kEncodeBlock) void encode_kernel(
     const int64_t extra = head + (n - tail0);
     for (int64_t e = threadIdx.x; e < extra; e += kEncodeBlock) {
       const int64_t i = e < head ? e : tail0 + (e - head);
-      const float xi = ST::load(reinterpret_cast<const raw *>(x)[i]);
+      const val xi = ST::load(reinterpret_cast<const raw *>(x)[i]);
       for (int j = 0; j < nfreq; ++j) {
-        const float in[1] = {xi * __uint_as_float(uint32_t(127 + j) << 23)};
-        float out[2];
+        const val in[1] = {xi * pow2(j, val())};
+        val out[2];
         Core::apply(in, out, tb, 0u);
         reinterpret_cast<raw *>(y + (2 * j) * plane)[i] = ST::store(out[0]);
         reinterpret_cast<raw *>(y + (2 * j + 1) * plane)[i] = ST::store(out[1]);
@@ -472,7 +617,7 @@ template <class ST>
 hipError_t launch_encode(const void *x, void *y, int64_t n, int nfreq,
                          hipStream_t stream) {
   using raw = typename ST::raw;
-  constexpr int VEC = Vec<ST>::kElems;
+  constexpr int VEC = ST::kVec;
   const uintptr_t mis = uintptr_t(x) & 15u;
   const bool vec_ok = (uintptr_t(y) & 15u) == mis && mis % sizeof(raw) == 0 &&
                       (n * int64_t(sizeof(raw))) % 16 == 0;
@@ -515,7 +660,7 @@ template <class ST, class Op>
 hipError_t launch_map(const void *const *in, void *const *out, int64_t n,
                       hipStream_t stream, uint32_t flags) {
   using raw = typename ST::raw;
-  constexpr int VEC = Vec<ST>::kElems;
+  constexpr int VEC = ST::kVec;
   IoPtrs io{};
   io.flags = flags;
   const uintptr_t mis = uintptr_t(in[0]) & 15u;
@@ -554,6 +699,7 @@ hipError_t launch_dtype(ta_dtype dt, const void *const *in, void *const *out,
     case TA_F32: return launch_map<F32, Op>(in, out, n, s, flags);
     case TA_F16: return launch_map<F16, Op>(in, out, n, s, flags);
     case TA_BF16: return launch_map<BF16, Op>(in, out, n, s, flags);
+    case TA_F64: return launch_map<F64, Op>(in, out, n, s, flags);
   }
   return hipErrorInvalidValue;
 }
@@ -563,8 +709,12 @@ hipError_t launch_dtype(ta_dtype dt, const void *const *in, void *const *out,
 // ---------------------------------------------------------------------------
 thread_local int g_last_hip_error = 0;
 
-inline size_t dtype_size(ta_dtype dt) { return dt == TA_F32 ? 4 : 2; }
-inline bool dtype_ok(int dt) { return dt == TA_F32 || dt == TA_F16 || dt == TA_BF16; }
+inline size_t dtype_size(ta_dtype dt) {
+  return dt == TA_F64 ? 8 : (dt == TA_F32 ? 4 : 2);
+}
+inline bool dtype_ok(int dt) {
+  return dt == TA_F32 || dt == TA_F16 || dt == TA_BF16 || dt == TA_F64;
+}
 
 // Outputs may alias an input exactly; any other overlap is an error.
 inline bool overlap_ok(const void *const *in, int nin, void *const *out,
@@ -764,8 +914,8 @@ ta_status ta_tan_fwdbwd(const void *x, const void *gy, void *y, void *gx,
 ta_status ta_builtin_sincos(const void *x, void *ys, void *yc, void *yt,
                             int64_t n, int kind, ta_dtype dt, hipStream_t s) {
   if (!dtype_ok(dt)) return TA_EDTYPE;
-  if (dt != TA_F32) return TA_EDTYPE;
   if (kind < 0 || kind > 2) return TA_EINVAL;
+  if (dt != TA_F32 && !(dt == TA_F64 && kind != 1)) return TA_EDTYPE;
   const void *in[1] = {x};
   void *o3[3] = {ys, yc, yt};
   if (yt) {
@@ -840,6 +990,7 @@ ta_status ta_sincos_encode(const void *x, void *y, int64_t n, int nfreq,
     case TA_F32: e = launch_encode<F32>(x, y, n, nfreq, s); break;
     case TA_F16: e = launch_encode<F16>(x, y, n, nfreq, s); break;
     case TA_BF16: e = launch_encode<BF16>(x, y, n, nfreq, s); break;
+    case TA_F64: e = launch_encode<F64>(x, y, n, nfreq, s); break;
   }
   return finish(e);
 }

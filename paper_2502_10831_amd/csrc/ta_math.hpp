@@ -83,6 +83,7 @@ __host__ __device__ constexpr double kdet_of_row(int idx) {
 // One lane writes it with immediates; the caller synchronises.
 struct Tables {
   PieceRow row[8];
+  double kdet64[8];  // FP64 path
   float kdet[8];
   static constexpr bool kUsed = true;
   __device__ static void init(Tables &tb) {
@@ -91,9 +92,11 @@ struct Tables {
       for (int i = 0; i < 6; ++i) {
         const int slot = i < 3 ? i : i + 1;
         tb.row[slot] = piece_row(i);
+        tb.kdet64[slot] = kdet_of_row(i);
         tb.kdet[slot] = float(kdet_of_row(i));
       }
       tb.row[3] = tb.row[7] = PieceRow{0.0, 0.0, 1.0, 0.0};
+      tb.kdet64[3] = tb.kdet64[7] = 0.0;
       tb.kdet[3] = tb.kdet[7] = 0.0f;
     }
   }
@@ -202,19 +205,26 @@ __device__ inline Folded fold(float x) {
 //   sin: c ^ (a & ~b)   (q1 ^ sr for even q, q1 for odd q)
 //   cos: c ^ (b & ~a)   (q1 for even q, q1 ^ 1 ^ sr for odd q)
 //   tan: a ^ b
-__device__ inline uint32_t sin_mask(const Folded &f) {
+template <class F>
+__device__ inline uint32_t sin_mask(const F &f) {
   return (f.q << 30) ^ (f.hr & ~(f.q << 31));
 }
-__device__ inline uint32_t cos_mask(const Folded &f) {
+template <class F>
+__device__ inline uint32_t cos_mask(const F &f) {
   return (f.q << 30) ^ ((f.q << 31) & ~f.hr);
 }
-__device__ inline uint32_t tan_mask(const Folded &f) { return f.hr ^ (f.q << 31); }
+template <class F>
+__device__ inline uint32_t tan_mask(const F &f) { return f.hr ^ (f.q << 31); }
 
 // Applies the sign in bit 31 of m to v: v ^ (m & 0x80000000).  The unsigned
 // values of the method (N y, D y, N/D with N, D >= 0) and of the Taylor
 // series on [0, pi/2] are non-negative, so this sets the sign.
 __device__ inline float flip_sign(float v, uint32_t m) {
   return __uint_as_float(__float_as_uint(v) ^ (m & 0x80000000u));
+}
+__device__ inline double flip_sign(double v, uint32_t m) {
+  return __longlong_as_double(__double_as_longlong(v) ^
+                              (int64_t(m & 0x80000000u) << 32));
 }
 
 // ---------------------------------------------------------------------------
@@ -314,6 +324,253 @@ __device__ inline float taylor_tan_unsigned(float rho) {
 #pragma unroll
   for (int j = TERMS - 2; j >= 0; --j)
     s = __builtin_fmaf(s, z, float(tan_coef(j)));
+  return s * rho;
+}
+
+// ---------------------------------------------------------------------------
+// FP64 storage: the same method with every stage in FP64.
+//   Reduction to a double-double r = rh + rl (|r| <= pi/4, relative error
+//   below 2^-69 for every finite double): Cody-Waite with a three-word pi/2
+//   below 2^29, a 2/pi bit-table reduction above.  t = |r| 180/pi with a
+//   two-word constant, N and D by one FMA each, Q = N^2 + D^2, an inverse
+//   square root and a reciprocal refined to full FP64 precision.
+// ---------------------------------------------------------------------------
+constexpr double kPio2Lo2 = -0x1.f1976b7ed8fbcp-110;   // RN(pi/2 - Hi - Lo)
+constexpr double kDegPerRadLo = -0x1.1e7ab456405f9p-49;  // RN(180/pi - kDegPerRad)
+constexpr double kPio4 = 0x1.921fb54442d18p-1;          // RN(pi/4)
+constexpr double kLargeArg64 = 0x1p29;
+
+// Bits of 2/pi for the FP64 bit-table reduction: word 0 is zero (bits -31
+// to 0 of the expansion), word w holds bits 32(w-1)+1 .. 32w.
+__constant__ uint32_t kTwoOverPiBits64[40] = {
+    0x00000000u, 0xA2F9836Eu, 0x4E441529u, 0xFC2757D1u, 0xF534DDC0u,
+    0xDB629599u, 0x3C439041u, 0xFE5163ABu, 0xDEBBC561u, 0xB7246E3Au,
+    0x424DD2E0u, 0x06492EEAu, 0x09D1921Cu, 0xFE1DEB1Cu, 0xB129A73Eu,
+    0xE88235F5u, 0x2EBB4484u, 0xE99C7026u, 0xB45F7E41u, 0x3991D639u,
+    0x835339F4u, 0x9C845F8Bu, 0xBDF9283Bu, 0x1FF897FFu, 0xDE05980Fu,
+    0xEF2F118Bu, 0x5A0A6D1Fu, 0x6D367ECFu, 0x27CB09B7u, 0x4F463F66u,
+    0x9E5FEA2Du, 0x7527BAC7u, 0xEBE5F17Bu, 0x3D0739F7u, 0x8A5292EAu,
+    0x6BFB5FB1u, 0x1F8D5D08u, 0x56033046u, 0xFC7B6BABu, 0xF0CFBC20u};
+
+// Error-free transforms: a + b = s + e exactly (Knuth), and the same for
+// |a| >= |b| with three operations (Dekker).
+__device__ inline void two_sum(double a, double b, double &s, double &e) {
+  s = a + b;
+  const double bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+__device__ inline void fast_two_sum(double a, double b, double &s, double &e) {
+  s = a + b;
+  e = b - (s - a);
+}
+
+// |x| >= 2^29 (and +-Inf).  x = m 2^e (m < 2^53, e in [-23, 971]); the 2/pi
+// bits from 2^-(e-1) down, a 192-bit window, times m give x 2/pi mod 4: the
+// quadrant in the top two bits and a 190-bit fraction, which is rounded to
+// nearest (read as a signed number), summed exactly into a double-double
+// and multiplied by pi/2.  The window's truncation is below 2^-137 in the
+// fraction, far under the smallest |r| of any double (~2^-61).
+__device__ inline void reduce_large64(double x, double &rh, double &rl,
+                                      uint32_t &q) {
+  const uint64_t ux = uint64_t(__double_as_longlong(x));
+  const uint32_t ex = uint32_t(ux >> 52) & 0x7ffu;
+  if (ex == 0x7ffu) {  // +-Inf (NaN never reaches here)
+    rh = rl = __builtin_nan("");
+    q = 0;
+    return;
+  }
+  const int e = int(ex) - 1075;
+  const uint64_t m = (ux & 0xfffffffffffffull) | (1ull << 52);
+  const uint32_t ml = uint32_t(m), mh = uint32_t(m >> 32);
+  const int b0 = e + 30;  // (first needed bit, 1-based) + 31 >= 7
+  const int w0 = b0 >> 5, sh = b0 & 31;
+  uint32_t w[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const uint64_t pair = (uint64_t(kTwoOverPiBits64[w0 + k]) << 32) |
+                          kTwoOverPiBits64[w0 + k + 1];
+    w[k] = uint32_t(pair >> (32 - sh));
+  }
+  // P = m * W mod 2^192 (W = w[0] 2^160 + ... + w[5]) as 32-bit limbs p[L]
+  // of weight 2^(32 L): limb L gathers lo(ml w[5-L]), hi(ml w[6-L]),
+  // lo(mh w[6-L]) and hi(mh w[7-L]).
+  uint64_t a[6], b[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    a[k] = uint64_t(ml) * w[k];
+    b[k] = uint64_t(mh) * w[k];
+  }
+  uint32_t p[6];
+  uint64_t acc = a[5] & 0xffffffffu;
+  p[0] = uint32_t(acc);
+#pragma unroll
+  for (int L = 1; L < 6; ++L) {
+    acc = (acc >> 32) + (a[6 - L] >> 32) + (a[5 - L] & 0xffffffffu) +
+          (b[6 - L] & 0xffffffffu);
+    if (L >= 2) acc += b[7 - L] >> 32;
+    p[L] = uint32_t(acc);
+  }
+  // quadrant = bits 191..190; fraction = bits 189..0, rounded to nearest:
+  // a fraction >= 1/2 becomes (fraction - 1) with the next quadrant.
+  const uint32_t neg = (p[5] >> 29) & 1u;
+  uint32_t qq = (p[5] >> 30) + neg;
+  p[5] &= 0x3fffffffu;
+  // |fraction|: two's complement of the 190 bits when negative
+  const uint32_t flip = 0u - neg;
+  uint64_t carry = neg;
+#pragma unroll
+  for (int L = 0; L < 6; ++L) {
+    const uint64_t v = uint64_t(p[L] ^ flip) + carry;
+    p[L] = uint32_t(v);
+    carry = v >> 32;
+  }
+  p[5] &= 0x3fffffffu;
+  // |fraction| = sum p[L] 2^(32 L - 190), all terms >= 0: exact two-sums
+  double hi = double(p[5]) * 0x1p-30, lo = 0.0;
+#pragma unroll
+  for (int L = 4; L >= 0; --L) {
+    double e2;
+    two_sum(hi, double(p[L]) * __builtin_ldexp(1.0, 32 * L - 190), hi, e2);
+    lo += e2;
+  }
+  fast_two_sum(hi, lo, hi, lo);
+  // r = fraction * pi/2
+  double h = hi * kPio2Hi;
+  double l = __builtin_fma(hi, kPio2Hi, -h) + (hi * kPio2Lo + lo * kPio2Hi);
+  fast_two_sum(h, l, h, l);
+  if (neg) {
+    h = -h;
+    l = -l;
+  }
+  if (ux >> 63) {
+    h = -h;
+    l = -l;
+    qq = 0u - qq;
+  }
+  rh = h;
+  rl = l;
+  q = qq;
+}
+
+// x = q pi/2 + rh + rl for any double x.
+__device__ inline void reduce64(double x, double &rh, double &rl, uint32_t &q) {
+  const double qb = x * kTwoOverPi + kRoundMagic;
+  const double qd = qb - kRoundMagic;
+  q = uint32_t(__double2loint(qb));
+  const double r1 = __builtin_fma(-qd, kPio2Hi, x);  // exact
+  const double p = qd * kPio2Lo;
+  const double pe = __builtin_fma(qd, kPio2Lo, -p);  // qd Lo = p + pe
+  double s, se;
+  two_sum(r1, -p, s, se);
+  const double tail = __builtin_fma(-qd, kPio2Lo2, se - pe);
+  fast_two_sum(s, tail, rh, rl);
+  rh = __builtin_copysign(rh, s);  // keeps the sign of a zero x
+  if (__builtin_expect(__builtin_fabs(x) >= kLargeArg64, 0))
+    reduce_large64(x, rh, rl, q);
+  // x 2/pi is rounded before q is: q may be the neighbour of the nearest
+  // quadrant, leaving |r| a little above pi/4; move r into range
+  // (rh - Hi is exact there, by Sterbenz's lemma).
+  if (__builtin_expect(__builtin_fabs(rh) > kPio4, 0)) {
+    const double sg = rh > 0.0 ? 1.0 : -1.0;
+    const double h = rh - sg * kPio2Hi;
+    const double l = __builtin_fma(-sg, kPio2Lo2, rl - sg * kPio2Lo);
+    fast_two_sum(h, l, rh, rl);
+    q += rh < 0.0 ? 1u : 0xffffffffu;  // sign of the new r is opposite
+  }
+}
+
+struct Folded64 {
+  double rh, rl;  // reduced argument, |rh + rl| <= pi/4
+  double t;       // |r| in degrees, [0, 45]
+  uint32_t q;     // quadrant, low bits
+  uint32_t hr;    // high word of rh: bit 31 = sign of r
+  uint32_t row;   // LDS table slot j + 4*(q & 1)
+  __device__ double abs_r() const { return __builtin_fabs(rh); }
+  // rl with the sign of |r| (rh + rl = sign(rh) (|rh| + abs_rl()))
+  __device__ double abs_rl() const { return flip_sign(rl, hr); }
+};
+
+__device__ inline Folded64 fold64(double x) {
+  Folded64 f;
+  reduce64(x, f.rh, f.rl, f.q);
+  f.hr = uint32_t(__double2hiint(f.rh));
+  const double ra = f.abs_r();
+  f.t = __builtin_fma(ra, kDegPerRad,
+                      __builtin_fma(ra, kDegPerRadLo, f.abs_rl() * kDegPerRad));
+  const uint32_t j = f.t >= 30.0 ? 2u : (f.t >= 15.0 ? 1u : 0u);
+  f.row = ((f.q << 2) & 4u) | j;
+  return f;
+}
+
+struct Forms64 {
+  double n, d, q;
+};
+__device__ inline Forms64 forms64(const Folded64 &f, const Tables &tb) {
+  const PieceRow c = tb.row[f.row];
+  const double nd = __builtin_fma(c.sN, f.t, c.iN);
+  const double dd = __builtin_fma(c.sD, f.t, c.iD);
+  return Forms64{nd, dd, __builtin_fma(nd, nd, dd * dd)};
+}
+
+// 1/sqrt(q), q in [10^5, 10^7]: hardware estimate, one Newton step, then a
+// second whose residual 1 - q y^2 is formed exactly from y^2 = p + pe.
+__device__ inline double rsqrt64_refined(double q) {
+  double y = __builtin_amdgcn_rsq(q);
+  y = __builtin_fma(0.5 * y, __builtin_fma(-(q * y), y, 1.0), y);
+  const double p = y * y;
+  const double pe = __builtin_fma(y, y, -p);
+  double e = __builtin_fma(-q, p, 1.0);
+  e = __builtin_fma(-q, pe, e);
+  return __builtin_fma(0.5 * y, e, y);
+}
+// 1/d: hardware estimate and two Newton steps.
+__device__ inline double rcp64_refined(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  r = __builtin_fma(__builtin_fma(-d, r, 1.0), r, r);
+  return __builtin_fma(__builtin_fma(-d, r, 1.0), r, r);
+}
+// n/d: quotient from the refined reciprocal, exact residual, correction.
+__device__ inline double div64_refined(double n, double d) {
+  const double r = rcp64_refined(d);
+  const double t0 = n * r;
+  return __builtin_fma(__builtin_fma(-d, t0, n), r, t0);
+}
+
+// rho in FP64 (a for even q, pi/2 - a for odd q).
+__device__ inline double fold_rho64(const Folded64 &f) {
+  return (f.q & 1u) ? (kPio2Hi - f.abs_r()) + (kPio2Lo - f.abs_rl())
+                    : f.abs_r();
+}
+
+// FP64 Taylor baseline: the same terms with FP64 coefficients and Horner.
+__host__ __device__ constexpr double sin_coef64(int j) {
+  return ((j & 1) ? -1.0 : 1.0) / factorial(2 * j + 1);
+}
+__host__ __device__ constexpr double cos_coef64(int j) {
+  return ((j & 1) ? -1.0 : 1.0) / factorial(2 * j);
+}
+template <int TERMS>
+__device__ inline double taylor_sin_unsigned(double rho) {
+  const double z = rho * rho;
+  double s = sin_coef64(TERMS - 1);
+#pragma unroll
+  for (int j = TERMS - 2; j >= 0; --j) s = __builtin_fma(s, z, sin_coef64(j));
+  return s * rho;
+}
+template <int TERMS>
+__device__ inline double taylor_cos_unsigned(double rho) {
+  const double z = rho * rho;
+  double s = cos_coef64(TERMS - 1);
+#pragma unroll
+  for (int j = TERMS - 2; j >= 0; --j) s = __builtin_fma(s, z, cos_coef64(j));
+  return s;
+}
+template <int TERMS>
+__device__ inline double taylor_tan_unsigned(double rho) {
+  const double z = rho * rho;
+  double s = tan_coef(TERMS - 1);
+#pragma unroll
+  for (int j = TERMS - 2; j >= 0; --j) s = __builtin_fma(s, z, tan_coef(j));
   return s * rho;
 }
 

@@ -62,6 +62,34 @@ def log_magnitude(n: int = 1 << 26, seed: int | None = None) -> np.ndarray:
     return (sign * mag).astype(np.float32)
 
 
+def protocol_f64(n: int = 1 << 27, seed: int | None = None,
+                 chunk: int = 1 << 24) -> np.ndarray:
+    """The paper's benchmark angles (Section 4): U[-1e6, 1e6] in FP64."""
+    rng = _rng(seed)
+    out = np.empty(n, np.float64)
+    for s in range(0, n, chunk):
+        m = min(chunk, n - s)
+        out[s:s + m] = rng.uniform(-1e6, 1e6, m)
+    return out
+
+
+def log_magnitude_f64(n: int, seed: int | None = None) -> np.ndarray:
+    """|x| = 10^U[-300, 300], random sign: every FP64 exponent range, most
+    of it through the large-|x| reduction.  FP64."""
+    rng = _rng(seed)
+    mag = 10.0 ** rng.uniform(-300.0, 300.0, n)
+    return np.where(rng.random(n) < 0.5, -mag, mag)
+
+
+def exponent_sweep_f64(per_exp: int = 16, seed: int | None = None):
+    """per_exp random significands at every binary exponent of FP64 (normal
+    and subnormal), both signs."""
+    rng = _rng(seed)
+    e = np.repeat(np.arange(-1074, 1024), per_exp)
+    x = np.ldexp(1.0 + rng.random(e.size), e)
+    return np.where(rng.random(e.size) < 0.5, -x, x)
+
+
 def normal_pair(shape, sigma_x: float, seed: int | None = None):
     """x ~ N(0, sigma_x^2), upstream gradient g ~ N(0, 1); FP32."""
     rng = _rng(seed)

@@ -12,7 +12,7 @@ LIB = os.path.join(ROOT, "paper_2502_10831_amd", "libta.so")
 HEADER = os.path.join(ROOT, "include", "ta.h")
 
 OK, EINVAL, EDTYPE, EOVERLAP, EHIP = range(5)
-F32, F16, BF16 = range(3)
+F32, F16, BF16, F64 = range(4)
 A, B = 0x100000, 0x200000   # fake device addresses: never dereferenced
 
 
@@ -64,7 +64,9 @@ def test_sincos_validation(lib):
     assert f(A, B, B + 32, None, 16, F32, 2, None) == EINVAL  # unknown flag
     assert f(A, B, B + 32, B + 16, 16, F32, 0, None) == EOVERLAP
     assert f(A, B, B, None, 16, F32, 0, None) == EOVERLAP     # ys == yc
-    assert f(A, B, B + 64, B + 128, 16, 3, 0, None) == EDTYPE
+    assert f(A, B, B + 64, B + 128, 16, 4, 0, None) == EDTYPE
+    # FP64 elements are 8 bytes: 16 of them end at +128
+    assert f(A, B, B + 64, None, 16, F64, 0, None) == EOVERLAP
     assert f(A, B, B + 64, None, 0, F32, 0, None) == OK
     g = _fn(lib, "ta_tan_ex", vp, vp, i64, i32, u32, vp)
     assert g(A, B, 16, F32, 4, None) == EINVAL
@@ -85,6 +87,7 @@ def test_backward_validation(lib):
         assert f(A, None, B, 16, F32, None) == EINVAL
         assert f(A, B, A + 8, 16, F32, None) == EOVERLAP
         assert f(A, B, B + 4, 16, F32, None) == EOVERLAP
+        assert f(A, B, B + 64, 16, F64, None) == EOVERLAP
         assert f(A, B, None, 0, F32, None) == OK
     f = _fn(lib, "ta_sincos_bwd", vp, vp, vp, vp, i64, i32, vp)
     assert f(A, None, None, B, 16, F32, None) == EINVAL      # no gradient
@@ -124,6 +127,9 @@ def test_comparator_validation(lib):
     f = _fn(lib, "ta_builtin_sincos", vp, vp, vp, vp, i64, i32, i32, vp)
     assert f(A, B, B + 256, None, 16, 0, F16, None) == EDTYPE
     assert f(A, B, B + 256, None, 16, 3, F32, None) == EINVAL
+    # no FP64 hardware approximations: kind 1 is FP32 only
+    assert f(A, B, B + 256, None, 16, 1, F64, None) == EDTYPE
+    assert f(A, B, B + 256, None, 16, 0, BF16, None) == EDTYPE
     c = _fn(lib, "ta_copy", ctypes.POINTER(vp), i32, ctypes.POINTER(vp), i32,
             i64, i32, vp)
     ins = (vp * 1)(A)
