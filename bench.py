@@ -341,7 +341,7 @@ def extras(args, torch, ta, dev):
 def sq_per_elem():
     """VALU instructions per element from the committed SQ summary (None
     when it was taken on other kernel sources)."""
-    path = os.path.join(ROOT, "profiles", "ta_kernels_f32_bf16_sq_instructions.txt")
+    path = os.path.join(ROOT, "profiles", "ta_kernels_f32_bf16_f64_sq_instructions.txt")
     if not os.path.exists(path):
         return {}
     out, sha = {}, None
@@ -358,7 +358,9 @@ def sq_per_elem():
 def other_workloads(args, torch, ta, dev):
     """The remaining workload shapes, each timed with HIP events:
     2^29 FP16 / BF16 U[-pi, pi] (fused sin+cos+tan and sin), 2^26 FP32 with
-    |x| = 10^U[0,6], and the [64, 4096, 256] activation (FP32 and BF16)."""
+    |x| = 10^U[0,6], 2^27 FP64 U[-1e6, 1e6] (with the device library's
+    double functions beside it) and 2^26 FP64 with |x| = 10^U[-300, 300],
+    and the [64, 4096, 256] activation (FP32 and BF16)."""
     res = {}
     steps = max(5, args.steps // 2)
     valu = sq_per_elem()
@@ -407,6 +409,33 @@ def other_workloads(args, torch, ta, dev):
         "elements_on_bit_table_reduction": int((x.abs() >= 2.0 ** 29).sum())}
     del x, a, b, c
 
+    # FP64: the paper's benchmark angles U[-1e6, 1e6] in double, 2^27 of
+    # them (32 B/element fused), beside the device library's double
+    # sin/cos/tan in the same skeleton and a copy of the same byte mix
+    n = 1 << 27
+    x = torch.rand(n, device=dev, generator=gen, dtype=torch.float64) * 2e6 - 1e6
+    a, b, c = (torch.empty_like(x) for _ in range(3))
+    log("timing 2^27 FP64")
+    ms3 = timed(lambda: ta.ta_sincos(x, a, b, c))
+    ms1 = timed(lambda: ta.ta_sin(x, a))
+    msb = timed(lambda: ta.ta_builtin_sincos(x, a, b, c, 0))
+    msc = timed(lambda: ta.ta_copy([x], [a, b, c]))
+    xl = torch.from_numpy(wl.log_magnitude_f64(1 << 26)).to(dev)
+    msl = timed(lambda: ta.ta_sincos(xl, a[:1 << 26], b[:1 << 26], c[:1 << 26]))
+    res["f64_2p27_uniform_1e6"] = {
+        "sincos_tan": {"gelem_s": round(n / (ms3 * 1e-3) / 1e9, 1),
+                       "gbs_algorithmic": round(32 * n / (ms3 * 1e-3) / 1e9, 1),
+                       "hbm_frac": round(32 * n / (ms3 * 1e-3) / 1e9
+                                         / HBM_PEAK_GBS, 4)},
+        "sin": {"gelem_s": round(n / (ms1 * 1e-3) / 1e9, 1),
+                "gbs_algorithmic": round(16 * n / (ms1 * 1e-3) / 1e9, 1)},
+        "builtin_sin_cos_tan_f64": {"gelem_s": round(n / (msb * 1e-3) / 1e9, 1)},
+        "speedup_vs_builtin": round(msb / ms3, 3),
+        "copy_1in_3out_gbs": round(32 * n / (msc * 1e-3) / 1e9, 1),
+        "log_magnitude_2p26_sincos_tan_gelem_s": round(
+            (1 << 26) / (msl * 1e-3) / 1e9, 1)}
+    del x, a, b, c, xl
+
     shape = (64, 4096, 256)
     n = 64 * 4096 * 256
     xf = torch.randn(n, device=dev, generator=gen) * 3.0
@@ -440,7 +469,8 @@ def profile_pass(args, torch, ta, dev, x, ys, yc, yt):
     """Dispatches, in order, PROFILE_STEPS of each: ta_sincos (sin+cos+tan,
     2^28 FP32); copy 1 in -> 1 out (2^28 FP32, the counter calibration);
     ta_sin_fwdbwd ([128, 8192, 512] FP32); ta_sin (2^28 FP32); ta_sincos
-    and ta_sin on 2^29 BF16 U[-pi, pi]."""
+    and ta_sin on 2^29 BF16 U[-pi, pi]; ta_sincos on 2^27 FP64
+    U[-1e6, 1e6]."""
     for _ in range(PROFILE_STEPS):
         ta.ta_sincos(x, ys, yc, yt)
     torch.cuda.synchronize()
@@ -472,6 +502,14 @@ def profile_pass(args, torch, ta, dev, x, ys, yc, yt):
         ta.ta_sin(xb, bs)
     torch.cuda.synchronize()
     log("profiled BF16 ta_sincos / ta_sin")
+    del xb, bs, bc, bt
+    xd = torch.rand(1 << 27, device=dev, generator=gen,
+                    dtype=torch.float64) * 2e6 - 1e6
+    ds, dc, dt = (torch.empty_like(xd) for _ in range(3))
+    for _ in range(PROFILE_STEPS):
+        ta.ta_sincos(xd, ds, dc, dt)
+    torch.cuda.synchronize()
+    log("profiled FP64 ta_sincos")
     print(json.dumps({"profile_pass": "done", "source_sha": source_hash()}))
 
 
@@ -482,10 +520,12 @@ KERNELS = {
     "sin_f32": ("F32", "FwdOp<1, false>"),
     "sincos_tan_bf16": ("BF16", "FwdOp<7, false>"),
     "sin_bf16": ("BF16", "FwdOp<1, false>"),
+    "sincos_tan_f64": ("F64", "FwdOp<7, false>"),
 }
 ELEMS = {"sincos_tan_f32": 1 << 28, "copy_1to1_f32": 1 << 28,
          "sin_fwdbwd_f32": 128 * 8192 * 512, "sin_f32": 1 << 28,
-         "sincos_tan_bf16": 1 << 29, "sin_bf16": 1 << 29}
+         "sincos_tan_bf16": 1 << 29, "sin_bf16": 1 << 29,
+         "sincos_tan_f64": 1 << 27}
 VALU_PEAK = 256 * 4 * 16 * 2.4e9  # lane-instructions/s (VALU issue)
 
 
@@ -515,9 +555,11 @@ def summarize(a):
         # sizes, so keep the dispatches of the headline shapes (grid = one
         # thread per 16-byte FP32 vector of the workload)
         grids = {"sincos_tan_f32": (1 << 28) // 4,
-                 "sin_fwdbwd_f32": 128 * 8192 * 512 // 4}
+                 "sin_fwdbwd_f32": 128 * 8192 * 512 // 4,
+                 "sincos_tan_f64": (1 << 27) // 2}
         algo = {"sincos_tan_f32": 16 * (1 << 28),
-                "sin_fwdbwd_f32": 16 * 128 * 8192 * 512}
+                "sin_fwdbwd_f32": 16 * 128 * 8192 * 512,
+                "sincos_tan_f64": 32 * (1 << 27)}
         durs = {}
         for r in _csv_rows(directory, "kernel_trace.csv"):
             key = _which(r.get("Kernel_Name", ""))
@@ -566,7 +608,8 @@ def summarize(a):
             lines.append(f"fetch_scale: {fs:.4f}")
             lines.append(f"write_scale: {ws:.4f}")
             for key, alg in (("sincos_tan_f32", 16 * (1 << 28)),
-                             ("sin_fwdbwd_f32", 16 * 128 * 8192 * 512)):
+                             ("sin_fwdbwd_f32", 16 * 128 * 8192 * 512),
+                             ("sincos_tan_f64", 32 * (1 << 27))):
                 f_ = avg.get((key, "FETCH_SIZE"))
                 w_ = avg.get((key, "WRITE_SIZE"))
                 if f_ is None or w_ is None:

@@ -398,9 +398,9 @@ struct IoPtrs {
 };
 
 // Launch shape of the vector body, per kernel category, chosen by timing on
-// MI355X (2^28-2^29 elements):
-//   one input, several FP32 outputs: 256 threads, one 16-byte access per
-//     stream per thread, nontemporal stores;
+// MI355X (2^27-2^29 elements):
+//   one input, several FP32 or FP64 outputs: 256 threads, one 16-byte access
+//     per stream per thread, nontemporal stores;
 //   one output, or 16-bit storage (VALU-bound): two accesses per thread;
 //   two or more inputs (backward, fused forward+backward): 128 threads, one
 //     access, nontemporal loads and stores.
@@ -418,19 +418,11 @@ struct Shape {
 #ifndef TA_SHAPE_TWOIN
 #define TA_SHAPE_TWOIN {128, 1, true, true}
 #endif
-#ifndef TA_SHAPE_F64
-#define TA_SHAPE_F64 {256, 2, false, true}
-#endif
-#ifndef TA_SHAPE_F64_TWOIN
-#define TA_SHAPE_F64_TWOIN {128, 2, true, true}
-#endif
 
 template <class ST, class Op>
 constexpr Shape shape_for() {
-  if (sizeof(typename ST::raw) == 8)
-    return Op::NIN >= 2 ? Shape TA_SHAPE_F64_TWOIN : Shape TA_SHAPE_F64;
   if (Op::NIN >= 2) return Shape TA_SHAPE_TWOIN;
-  if (Op::NOUT >= 2 && sizeof(typename ST::raw) == 4) return Shape TA_SHAPE_MULTI;
+  if (Op::NOUT >= 2 && sizeof(typename ST::raw) >= 4) return Shape TA_SHAPE_MULTI;
   return Shape TA_SHAPE_SINGLE;
 }
 
