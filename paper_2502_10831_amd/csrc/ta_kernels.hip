@@ -20,7 +20,9 @@ namespace ta {
 // ---------------------------------------------------------------------------
 // Storage formats.  `val` is the arithmetic type of the element functors:
 // FP32 for the FP32 and 16-bit formats (loads widen exactly, stores round
-// to nearest even), FP64 for FP64.  unpack/pack convert one 16-byte access.
+// to nearest even), FP64 for FP64.  unpack/pack convert one 16-byte access
+// (unpack copies the bytes out: reading lanes of a vector that is only
+// loaded under a branch makes the compiler zero it first).
 // ---------------------------------------------------------------------------
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
@@ -34,8 +36,7 @@ struct F32 {
   static __device__ val load(raw v) { return __uint_as_float(v); }
   static __device__ raw store(val f) { return __float_as_uint(f); }
   static __device__ void unpack(const u32x4 &w, val *v) {
-#pragma unroll
-    for (int e = 0; e < 4; ++e) v[e] = __uint_as_float(w[e]);
+    __builtin_memcpy(v, &w, 16);
   }
   static __device__ u32x4 pack(const val *v) {
     u32x4 w;
@@ -53,9 +54,10 @@ struct Half16 {
   using val = float;
   static constexpr int kVec = 8;
   static __device__ void unpack(const u32x4 &w, val *v) {
+    raw h[8];
+    __builtin_memcpy(h, &w, 16);
 #pragma unroll
-    for (int e = 0; e < 8; ++e)
-      v[e] = Derived::load(uint16_t(w[e >> 1] >> (16 * (e & 1))));
+    for (int e = 0; e < 8; ++e) v[e] = Derived::load(h[e]);
   }
   static __device__ u32x4 pack(const val *v) {
     u32x4 w;
@@ -94,9 +96,7 @@ struct F64 {
   static __device__ val load(raw v) { return __longlong_as_double(int64_t(v)); }
   static __device__ raw store(val f) { return raw(__double_as_longlong(f)); }
   static __device__ void unpack(const u32x4 &w, val *v) {
-#pragma unroll
-    for (int e = 0; e < 2; ++e)
-      v[e] = load((uint64_t(w[2 * e + 1]) << 32) | w[2 * e]);
+    __builtin_memcpy(v, &w, 16);
   }
   static __device__ u32x4 pack(const val *v) {
     u32x4 w;
