@@ -34,6 +34,14 @@ def test_reduction_constants(text):
     assert _const(text, "kDegPerRad") == float(180 / pi)
     assert _const(text, "kRoundMagic") == 1.5 * 2.0 ** 52
     assert _const(text, "kPi12") == float(pi / 12)
+    # FP64 path: third word of pi/2, the low word of 180/pi, pi/4
+    lo = _const(text, "kPio2Lo")
+    assert _const(text, "kPio2Lo2") == float(pi / 2 - mpmath.mpf(hi) -
+                                             mpmath.mpf(lo))
+    k = _const(text, "kDegPerRad")
+    assert _const(text, "kDegPerRadLo") == float(180 / pi - mpmath.mpf(k))
+    assert _const(text, "kPio4") == float(pi / 4)
+    assert _const(text, "kLargeArg64") == 2.0 ** 29
 
 
 def test_two_over_pi_bits(text):
@@ -46,6 +54,27 @@ def test_two_over_pi_bits(text):
         top = int(mpmath.floor(x))
         assert w == top
         x -= top
+
+
+def test_two_over_pi_bits_fp64(text):
+    """Word 0 is zero (bits -31..0); word w holds bits 32(w-1)+1 .. 32w; the
+    table must reach the last word the reduction of the largest double
+    reads (exponent 971: words up to 31 + 6)."""
+    mpmath.mp.prec = 2000
+    m = re.search(r"kTwoOverPiBits64\[(\d+)\] = \{([^}]*)\}", text)
+    size = int(m.group(1))
+    words = [int(w.strip().rstrip("u"), 16) for w in m.group(2).split(",")]
+    assert len(words) == size and words[0] == 0
+    x = 2 / mpmath.pi
+    for w in words[1:]:
+        x *= 2 ** 32
+        top = int(mpmath.floor(x))
+        assert w == top
+        x -= top
+    e_max = 2046 - 1075
+    w0 = (e_max + 30) >> 5
+    assert w0 + 6 < size
+    assert (-23 + 30) >> 5 >= 0   # smallest exponent on the large path
 
 
 def test_piece_integers_match_appendix(text, golden_dir):
