@@ -65,10 +65,15 @@ enum {
    * sign is applied, when the folded angle is within 1e-3 of pi/2.  Off by
    * default (the formula is then used all the way to the pole). */
   TA_FLAG_TAN_GUARD = 1u,
+  /* Reduce the argument in FP64.  Accepted by every call that takes flags
+   * and changes nothing: every reduction here is already FP64 (Cody-Waite
+   * below 2^29, a 2/pi bit-table reduction above).  Bit 4u (an FP32
+   * reduction) is not provided and is rejected with TA_EINVAL. */
+  TA_FLAG_FORCE_FP64_REDUCTION = 2u,
   /* ta_paper_sincos only: index the pieces by floor(rho / 0.261) as the
    * pseudocode of proposed_sin / proposed_tan does (clamped to the last
    * piece) instead of the pi/12 intervals of Section 2. */
-  TA_FLAG_LITERAL_DIVISOR = 2u
+  TA_FLAG_LITERAL_DIVISOR = 8u
 };
 
 /* ---- forward: the proposed functions (Section 2 formulas, Section 3 fold) */
@@ -87,7 +92,8 @@ ta_status ta_tan(const void *x, void *y, int64_t n, ta_dtype dt,
  * not NULL, yt = tan_a.  `ys` and `yc` are required. */
 ta_status ta_sincos(const void *x, void *ys, void *yc, void *yt, int64_t n,
                     ta_dtype dt, hipStream_t stream);
-/* Same as above with flag bits (TA_FLAG_TAN_GUARD affects tan outputs). */
+/* Same as above with flag bits (TA_FLAG_TAN_GUARD affects tan outputs;
+ * TA_FLAG_FORCE_FP64_REDUCTION is accepted). */
 ta_status ta_tan_ex(const void *x, void *y, int64_t n, ta_dtype dt,
                     uint32_t flags, hipStream_t stream);
 ta_status ta_sincos_ex(const void *x, void *ys, void *yc, void *yt, int64_t n,
@@ -140,7 +146,7 @@ ta_status ta_tan_fwdbwd(const void *x, const void *gy, void *y, void *gx,
  * are rounded to the storage dtype.  This reproduces the error statistics of
  * Tables 1-3 (maximum sin/cos error 1.532e-3); it is ~3x less accurate than
  * ta_sincos.  Any non-empty subset of ys/yc/yt; flags: TA_FLAG_TAN_GUARD,
- * TA_FLAG_LITERAL_DIVISOR. */
+ * TA_FLAG_LITERAL_DIVISOR, TA_FLAG_FORCE_FP64_REDUCTION. */
 ta_status ta_paper_sincos(const void *x, void *ys, void *yc, void *yt,
                           int64_t n, ta_dtype dt, uint32_t flags,
                           hipStream_t stream);

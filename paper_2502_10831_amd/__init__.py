@@ -30,7 +30,8 @@ __all__ = [
     "ta_paper_sincos", "ta_sincos_encode", "ta_builtin_sincos", "ta_copy",
     "sin", "cos", "tan", "sincos", "taylor",
     "SinFn", "CosFn", "TanFn", "SinCosFn",
-    "TA_FLAG_TAN_GUARD", "TA_FLAG_LITERAL_DIVISOR", "paper_sincos", "encode",
+    "TA_FLAG_TAN_GUARD", "TA_FLAG_LITERAL_DIVISOR",
+    "TA_FLAG_FORCE_FP64_REDUCTION", "paper_sincos", "encode",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -38,7 +39,8 @@ _LIB = os.path.join(_HERE, "libta.so")
 
 TA_F32, TA_F16, TA_BF16, TA_F64 = 0, 1, 2, 3
 TA_FLAG_TAN_GUARD = 1
-TA_FLAG_LITERAL_DIVISOR = 2
+TA_FLAG_FORCE_FP64_REDUCTION = 2
+TA_FLAG_LITERAL_DIVISOR = 8
 _DTYPE_CODE = {torch.float32: TA_F32, torch.float16: TA_F16,
                torch.bfloat16: TA_BF16, torch.float64: TA_F64}
 

@@ -115,24 +115,31 @@ struct F64 {
 // ---------------------------------------------------------------------------
 enum : int { kSin = 1, kCos = 2, kTan = 4 };
 
-template <int MASK, bool GUARD>
+// LOW: the variant for 16-bit storage.  Its outputs keep 8 (BF16) or 11
+// (FP16) significant bits, so the hardware inverse square root and
+// reciprocal (each within about one FP32 ulp) are used without the Newton
+// refinement; the result stays within the FP32 tolerance before the 16-bit
+// rounding.  Every op names the instance the 16-bit formats launch (Low).
+template <int MASK, bool GUARD, bool LOW = false>
 struct FwdOp {
   static constexpr int NIN = 1;
   static constexpr int NOUT = ((MASK & kSin) ? 1 : 0) + ((MASK & kCos) ? 1 : 0) +
                               ((MASK & kTan) ? 1 : 0);
   using Table = Tables;
+  using Low = FwdOp<MASK, GUARD, true>;
   __device__ static void apply(const float *in, float *out, const Table &tb,
                                   uint32_t) {
     const Folded f = fold(in[0]);
     const Forms v = forms(f, tb);
     int o = 0;
     if constexpr ((MASK & (kSin | kCos)) != 0) {
-      const float y = rsqrt_refined(v.q);
+      const float y = LOW ? rsqrt_est(v.q) : rsqrt_refined(v.q);
       if constexpr (MASK & kSin) out[o++] = flip_sign(v.n * y, sin_mask(f));
       if constexpr (MASK & kCos) out[o++] = flip_sign(v.d * y, cos_mask(f));
     }
     if constexpr (MASK & kTan) {
-      float t = flip_sign(div_refined(v.n, v.d), tan_mask(f));
+      float t = flip_sign(LOW ? div_est(v.n, v.d) : div_refined(v.n, v.d),
+                          tan_mask(f));
       if constexpr (GUARD) {
         // Section 3 proposed_tan: +inf within 1e-3 of pi/2, before the sign.
         if ((f.q & 1u) && f.abs_r() < 1e-3) t = __builtin_inff();
@@ -165,6 +172,7 @@ struct TaylorOp {
   static constexpr int NIN = 1;
   static constexpr int NOUT = 1;
   using Table = NoTable;
+  using Low = TaylorOp;
   __device__ static void apply(const float *in, float *out, const Table &,
                                   uint32_t) {
     const Folded f = fold(in[0]);
@@ -193,23 +201,25 @@ struct TaylorOp {
 //   sin: gx = gy * omega * cos_a     cos: gx = -gy * omega * sin_a
 //   tan: gx = gy * (180/pi) det / D^2
 // WITH_Y also writes the forward value (the fused forward+backward).
-template <int WHICH, bool WITH_Y>
+template <int WHICH, bool WITH_Y, bool LOW = false>
 struct BwdOp {
   static constexpr int NIN = 2;  // x, gy
   static constexpr int NOUT = WITH_Y ? 2 : 1;
   using Table = Tables;
+  using Low = BwdOp<WHICH, WITH_Y, true>;
   __device__ static void apply(const float *in, float *out, const Table &tb,
                                   uint32_t) {
     const Folded f = fold(in[0]);
     const Forms v = forms(f, tb);
     const float kdet = tb.kdet[f.row];
     if constexpr (WHICH == kTan) {
-      const float r = rcp_refined(v.d);
+      const float r = LOW ? rcp_est(v.d) : rcp_refined(v.d);
       const float dt = kdet * r * r;
-      if constexpr (WITH_Y) out[0] = flip_sign(div_refined(v.n, v.d), tan_mask(f));
+      if constexpr (WITH_Y)
+        out[0] = flip_sign(LOW ? v.n * r : div_refined(v.n, v.d), tan_mask(f));
       out[WITH_Y ? 1 : 0] = in[1] * dt;
     } else {
-      const float y = rsqrt_refined(v.q);
+      const float y = LOW ? rsqrt_est(v.q) : rsqrt_refined(v.q);
       const float s = flip_sign(v.n * y, sin_mask(f));
       const float c = flip_sign(v.d * y, cos_mask(f));
       const float omega = kdet * y * y;
@@ -252,16 +262,17 @@ struct BwdOp {
 };
 
 // gx = gs * d sin_a/dx + gc * d cos_a/dx = omega (gs cos_a - gc sin_a).
-template <bool HAS_GS, bool HAS_GC>
+template <bool HAS_GS, bool HAS_GC, bool LOW = false>
 struct SinCosBwdOp {
   static constexpr int NIN = 1 + (HAS_GS ? 1 : 0) + (HAS_GC ? 1 : 0);
   static constexpr int NOUT = 1;
   using Table = Tables;
+  using Low = SinCosBwdOp<HAS_GS, HAS_GC, true>;
   __device__ static void apply(const float *in, float *out, const Table &tb,
                                   uint32_t) {
     const Folded f = fold(in[0]);
     const Forms v = forms(f, tb);
-    const float y = rsqrt_refined(v.q);
+    const float y = LOW ? rsqrt_est(v.q) : rsqrt_refined(v.q);
     const float omega = tb.kdet[f.row] * y * y;
     float acc = 0.0f;
     if constexpr (HAS_GS) acc = in[1] * flip_sign(v.d * y, cos_mask(f));
@@ -293,6 +304,7 @@ struct PaperOp {
   static constexpr int NOUT = ((MASK & kSin) ? 1 : 0) + ((MASK & kCos) ? 1 : 0) +
                               ((MASK & kTan) ? 1 : 0);
   using Table = PaperTables;
+  using Low = PaperOp;
   __device__ static void apply(const float *in, float *out, const Table &tb,
                                uint32_t flags) {
     const Folded f = fold(in[0]);
@@ -339,6 +351,7 @@ struct BuiltinOp {
   static constexpr int NIN = 1;
   static constexpr int NOUT = WITH_TAN ? 3 : 2;
   using Table = NoTable;
+  using Low = BuiltinOp;
   __device__ static void apply(const float *in, float *out, const Table &,
                                   uint32_t) {
     const float x = in[0];
@@ -381,6 +394,7 @@ struct CopyOp {
   static constexpr int NIN = NI;
   static constexpr int NOUT = NO;
   using Table = NoTable;
+  using Low = CopyOp;
   template <class V>
   __device__ static void apply(const V *in, V *out, const Table &, uint32_t) {
 #pragma unroll
@@ -553,7 +567,7 @@ __global__ __launch_bounds__(kEncodeBlock) void encode_kernel(
     const char *x, char *y, int64_t n, int nfreq, int64_t head, int64_t nvec) {
   using raw = typename ST::raw;
   using val = typename ST::val;
-  using Core = FwdOp<kSin | kCos, false>;
+  using Core = FwdOp<kSin | kCos, false, sizeof(raw) == 2>;
   constexpr int VEC = VEC_PATH ? ST::kVec : 1;
   __shared__ Tables tb;
   Tables::init(tb);
@@ -689,8 +703,8 @@ hipError_t launch_dtype(ta_dtype dt, const void *const *in, void *const *out,
                         int64_t n, hipStream_t s, uint32_t flags) {
   switch (dt) {
     case TA_F32: return launch_map<F32, Op>(in, out, n, s, flags);
-    case TA_F16: return launch_map<F16, Op>(in, out, n, s, flags);
-    case TA_BF16: return launch_map<BF16, Op>(in, out, n, s, flags);
+    case TA_F16: return launch_map<F16, typename Op::Low>(in, out, n, s, flags);
+    case TA_BF16: return launch_map<BF16, typename Op::Low>(in, out, n, s, flags);
     case TA_F64: return launch_map<F64, Op>(in, out, n, s, flags);
   }
   return hipErrorInvalidValue;
@@ -817,7 +831,8 @@ ta_status ta_cos(const void *x, void *y, int64_t n, ta_dtype dt, hipStream_t s) 
 
 ta_status ta_tan_ex(const void *x, void *y, int64_t n, ta_dtype dt,
                     uint32_t flags, hipStream_t s) {
-  if (flags & ~uint32_t(TA_FLAG_TAN_GUARD)) return TA_EINVAL;
+  if (flags & ~uint32_t(TA_FLAG_TAN_GUARD | TA_FLAG_FORCE_FP64_REDUCTION))
+    return TA_EINVAL;
   void *o[1] = {y};
   if (flags & TA_FLAG_TAN_GUARD) return fwd<kTan, true>(x, o, n, dt, s);
   return fwd<kTan, false>(x, o, n, dt, s);
@@ -829,7 +844,8 @@ ta_status ta_tan(const void *x, void *y, int64_t n, ta_dtype dt, hipStream_t s) 
 
 ta_status ta_sincos_ex(const void *x, void *ys, void *yc, void *yt, int64_t n,
                        ta_dtype dt, uint32_t flags, hipStream_t s) {
-  if (flags & ~uint32_t(TA_FLAG_TAN_GUARD)) return TA_EINVAL;
+  if (flags & ~uint32_t(TA_FLAG_TAN_GUARD | TA_FLAG_FORCE_FP64_REDUCTION))
+    return TA_EINVAL;
   if (yt) {
     void *o[3] = {ys, yc, yt};
     if (flags & TA_FLAG_TAN_GUARD)
@@ -946,7 +962,8 @@ ta_status ta_paper_sincos(const void *x, void *ys, void *yc, void *yt,
                           int64_t n, ta_dtype dt, uint32_t flags,
                           hipStream_t s) {
   if (!dtype_ok(dt)) return TA_EDTYPE;
-  if (flags & ~uint32_t(TA_FLAG_TAN_GUARD | TA_FLAG_LITERAL_DIVISOR))
+  if (flags & ~uint32_t(TA_FLAG_TAN_GUARD | TA_FLAG_LITERAL_DIVISOR |
+                       TA_FLAG_FORCE_FP64_REDUCTION))
     return TA_EINVAL;
   void *o[3];
   int m = 0, k = 0;

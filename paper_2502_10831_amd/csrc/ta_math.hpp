@@ -271,6 +271,11 @@ __device__ inline float rcp_refined(float d) {
   return __builtin_fmaf(__builtin_fmaf(-d, r, 1.0f), r, r);
 }
 
+// Unrefined hardware estimates, for outputs rounded to 16 bits.
+__device__ inline float rsqrt_est(float q) { return __builtin_amdgcn_rsqf(q); }
+__device__ inline float rcp_est(float d) { return __builtin_amdgcn_rcpf(d); }
+__device__ inline float div_est(float n, float d) { return n * rcp_est(d); }
+
 // ---------------------------------------------------------------------------
 // Taylor baseline: first `TERMS` Maclaurin terms on the folded angle rho.
 // ---------------------------------------------------------------------------

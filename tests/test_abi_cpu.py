@@ -61,7 +61,8 @@ def test_unary_validation(lib):
 def test_sincos_validation(lib):
     f = _fn(lib, "ta_sincos_ex", vp, vp, vp, vp, i64, i32, u32, vp)
     assert f(A, B, None, None, 16, F32, 0, None) == EINVAL    # yc required
-    assert f(A, B, B + 32, None, 16, F32, 2, None) == EINVAL  # unknown flag
+    assert f(A, B, B + 32, None, 16, F32, 4, None) == EINVAL  # FP32 reduction
+    assert f(A, B, B + 32, None, 16, F32, 8, None) == EINVAL  # paper-only flag
     assert f(A, B, B + 32, B + 16, 16, F32, 0, None) == EOVERLAP
     assert f(A, B, B, None, 16, F32, 0, None) == EOVERLAP     # ys == yc
     assert f(A, B, B + 64, B + 128, 16, 4, 0, None) == EDTYPE
@@ -70,6 +71,7 @@ def test_sincos_validation(lib):
     assert f(A, B, B + 64, None, 0, F32, 0, None) == OK
     g = _fn(lib, "ta_tan_ex", vp, vp, i64, i32, u32, vp)
     assert g(A, B, 16, F32, 4, None) == EINVAL
+    assert g(A, B, 16, F32, 16, None) == EINVAL
 
 
 def test_taylor_validation(lib):
@@ -105,6 +107,7 @@ def test_paper_validation(lib):
     assert f(A, None, None, None, 16, F32, 0, None) == EINVAL   # no output
     assert f(A, None, None, None, 0, F32, 0, None) == OK
     assert f(A, B, None, None, 16, F32, 4, None) == EINVAL      # bad flag
+    assert f(A, B, None, None, 16, F32, 16, None) == EINVAL
     assert f(A, B, None, None, 16, 5, 0, None) == EDTYPE
     assert f(A, B, B + 8, None, 16, F32, 3, None) == EOVERLAP
     assert f(None, B, None, None, 16, F32, 0, None) == EINVAL

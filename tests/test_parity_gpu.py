@@ -692,3 +692,22 @@ def test_comparators_and_copy(dev):
     ta.ta_copy([xd], outs)
     for o in outs:
         assert torch.equal(o, xd)
+
+
+def test_force_fp64_reduction_flag_changes_nothing(dev):
+    """The flag is accepted and every reduction is FP64 already: identical
+    bits with and without it, FP32 and FP64 storage, forward and paper."""
+    for dt in (torch.float32, torch.float64):
+        x = torch.from_numpy(wl.throughput_mix(1 << 16, seed=77)).to(dev).to(dt)
+        a = [torch.empty_like(x) for _ in range(3)]
+        b = [torch.empty_like(x) for _ in range(3)]
+        ta.ta_sincos_ex(x, *a, 0)
+        ta.ta_sincos_ex(x, *b, ta.TA_FLAG_FORCE_FP64_REDUCTION)
+        p = [torch.empty_like(x) for _ in range(3)]
+        q = [torch.empty_like(x) for _ in range(3)]
+        ta.ta_paper_sincos(x, *p, ta.TA_FLAG_LITERAL_DIVISOR)
+        ta.ta_paper_sincos(x, *q, ta.TA_FLAG_LITERAL_DIVISOR |
+                           ta.TA_FLAG_FORCE_FP64_REDUCTION)
+        torch.cuda.synchronize()
+        for u, v in zip(a + p, b + q):
+            assert torch.equal(u.view(torch.uint8), v.view(torch.uint8))
