@@ -370,6 +370,22 @@ def other_workloads(args, torch, ta, dev):
         per, total, _ = time_launches(fn, steps, 3, torch)
         return total / steps
 
+    import numpy as np
+
+    def libm_errors(x64, outs):
+        """Max |error| of sin/cos and max relative error of tan (|cos x| >
+        1e-3) against FP64 libm at the inputs x64."""
+        e = {}
+        ok = np.abs(np.cos(x64)) > 1e-3
+        for name, g in outs.items():
+            r = getattr(np, name)(x64)
+            if name == "tan":
+                k = ok & (r != 0)
+                e["tan_max_rel"] = float((np.abs(g[k] - r[k]) / np.abs(r[k])).max())
+            else:
+                e[f"{name}_max_abs"] = float(np.abs(g - r).max())
+        return e
+
     for tdt, tag in ((torch.bfloat16, "bf16"), (torch.float16, "f16")):
         n = 1 << 29
         x = (torch.rand(n, device=dev, generator=gen, dtype=torch.float64)
@@ -393,20 +409,36 @@ def other_workloads(args, torch, ta, dev):
                     "unit": "1e12 VALU lane-instructions/s",
                     "frac": round(lane_instr / VALU_PEAK, 3),
                     "valu_per_elem": valu[kind]}
+        # every input of this workload is one of the 16-bit patterns in
+        # [-pi, pi]: the errors over all of them are the workload's errors
+        pat = torch.arange(1 << 16, dtype=torch.int32, device=dev).to(
+            torch.int16).view(tdt)
+        pat = pat[torch.isfinite(pat) & (pat.float().abs() <= math.pi)]
+        ps, pc, pt = (torch.empty_like(pat) for _ in range(3))
+        ta.ta_sincos(pat, ps, pc, pt)
+        entry["error_vs_libm_over_inputs"] = libm_errors(
+            pat.double().cpu().numpy(),
+            {"sin": ps.double().cpu().numpy(), "cos": pc.double().cpu().numpy(),
+             "tan": pt.double().cpu().numpy()})
         res[f"{tag}_2p29_uniform_pi"] = entry
         del x, a, b, c
 
     n = 1 << 26
-    import numpy as np
     from paper_2502_10831_amd import workloads as wl
     x = torch.from_numpy(wl.log_magnitude(n)).to(dev)
     a, b, c = (torch.empty_like(x) for _ in range(3))
     log("timing 2^26 log-magnitude")
     ms = timed(lambda: ta.ta_sincos(x, a, b, c))
+    sample = slice(0, 1 << 20)
     res["f32_2p26_log_magnitude"] = {
         "sincos_tan_gelem_s": round(n / (ms * 1e-3) / 1e9, 1),
         "gbs_algorithmic": round(16 * n / (ms * 1e-3) / 1e9, 1),
-        "elements_on_bit_table_reduction": int((x.abs() >= 2.0 ** 29).sum())}
+        "elements_on_bit_table_reduction": int((x.abs() >= 2.0 ** 29).sum()),
+        "error_vs_libm_first_2p20": libm_errors(
+            x[sample].double().cpu().numpy(),
+            {"sin": a[sample].double().cpu().numpy(),
+             "cos": b[sample].double().cpu().numpy(),
+             "tan": c[sample].double().cpu().numpy()})}
     del x, a, b, c
 
     # FP64: the paper's benchmark angles U[-1e6, 1e6] in double, 2^27 of
@@ -434,6 +466,11 @@ def other_workloads(args, torch, ta, dev):
         "copy_1in_3out_gbs": round(32 * n / (msc * 1e-3) / 1e9, 1),
         "log_magnitude_2p26_sincos_tan_gelem_s": round(
             (1 << 26) / (msl * 1e-3) / 1e9, 1)}
+    ta.ta_sincos(x, a, b, c)
+    res["f64_2p27_uniform_1e6"]["error_vs_libm_first_2p20"] = libm_errors(
+        x[:1 << 20].cpu().numpy(),
+        {"sin": a[:1 << 20].cpu().numpy(), "cos": b[:1 << 20].cpu().numpy(),
+         "tan": c[:1 << 20].cpu().numpy()})
     del x, a, b, c, xl
 
     shape = (64, 4096, 256)
@@ -513,14 +550,16 @@ def profile_pass(args, torch, ta, dev, x, ys, yc, yt):
     print(json.dumps({"profile_pass": "done", "source_sha": source_hash()}))
 
 
+# kernel-name prefixes (the functors carry further template arguments, such
+# as the 16-bit variant flag)
 KERNELS = {
-    "sincos_tan_f32": ("F32", "FwdOp<7, false>"),
+    "sincos_tan_f32": ("F32", "FwdOp<7, false"),
     "copy_1to1_f32": ("F32", "CopyOp<1, 1>"),
-    "sin_fwdbwd_f32": ("F32", "BwdOp<1, true>"),
-    "sin_f32": ("F32", "FwdOp<1, false>"),
-    "sincos_tan_bf16": ("BF16", "FwdOp<7, false>"),
-    "sin_bf16": ("BF16", "FwdOp<1, false>"),
-    "sincos_tan_f64": ("F64", "FwdOp<7, false>"),
+    "sin_fwdbwd_f32": ("F32", "BwdOp<1, true"),
+    "sin_f32": ("F32", "FwdOp<1, false"),
+    "sincos_tan_bf16": ("BF16", "FwdOp<7, false"),
+    "sin_bf16": ("BF16", "FwdOp<1, false"),
+    "sincos_tan_f64": ("F64", "FwdOp<7, false"),
 }
 ELEMS = {"sincos_tan_f32": 1 << 28, "copy_1to1_f32": 1 << 28,
          "sin_fwdbwd_f32": 128 * 8192 * 512, "sin_f32": 1 << 28,

@@ -432,11 +432,15 @@ struct Shape {
 #ifndef TA_SHAPE_TWOIN
 #define TA_SHAPE_TWOIN {128, 1, true, true}
 #endif
+#ifndef TA_SHAPE_HALF
+#define TA_SHAPE_HALF {256, 2, false, true}
+#endif
 
 template <class ST, class Op>
 constexpr Shape shape_for() {
   if (Op::NIN >= 2) return Shape TA_SHAPE_TWOIN;
-  if (Op::NOUT >= 2 && sizeof(typename ST::raw) >= 4) return Shape TA_SHAPE_MULTI;
+  if (sizeof(typename ST::raw) == 2) return Shape TA_SHAPE_HALF;
+  if (Op::NOUT >= 2) return Shape TA_SHAPE_MULTI;
   return Shape TA_SHAPE_SINGLE;
 }
 
@@ -474,8 +478,11 @@ __device__ inline void scalar_element(const IoPtrs &io, int64_t i,
 // accesses per stream per thread, all loads issued before any compute.  The
 // workgroup with blockIdx 0 also does the scalar head [0, head) and tail
 // [head + nvec*VEC, n).
+#ifndef TA_MIN_BLOCKS
+#define TA_MIN_BLOCKS 1
+#endif
 template <class ST, class Op, int BLOCK, int UNROLL, bool NTL, bool NTS>
-__global__ __launch_bounds__(BLOCK) void map_vec_kernel(IoPtrs io, int64_t head,
+__global__ __launch_bounds__(BLOCK, TA_MIN_BLOCKS) void map_vec_kernel(IoPtrs io, int64_t head,
                                                         int64_t nvec, int64_t n) {
   using raw = typename ST::raw;
   constexpr int VEC = ST::kVec;
