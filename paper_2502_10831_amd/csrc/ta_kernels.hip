@@ -2,8 +2,9 @@
 //
 // Every entry point is an elementwise map: NIN input streams, NOUT output
 // streams, one functor per element.  The streaming skeleton issues 16-byte
-// global loads and stores (4 FP32 or 8 16-bit elements per access), with a
-// launch shape per kernel category (see shape_for) and 64-bit indexing.  The
+// global loads and stores (4 FP32 or 2 FP64 elements per access; 8-byte
+// accesses of 4 elements for 16-bit storage), with a launch shape per kernel
+// category (see shape_for) and 64-bit indexing.  The
 // per-piece coefficients live in LDS (one 200-byte copy per workgroup),
 // never in HBM.
 #include <hip/hip_runtime.h>
@@ -25,6 +26,7 @@ namespace ta {
 // loaded under a branch makes the compiler zero it first).
 // ---------------------------------------------------------------------------
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
@@ -32,6 +34,7 @@ typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 struct F32 {
   using raw = uint32_t;
   using val = float;
+  using vec = u32x4;
   static constexpr int kVec = 4;
   static __device__ val load(raw v) { return __uint_as_float(v); }
   static __device__ raw store(val f) { return __float_as_uint(f); }
@@ -47,22 +50,30 @@ struct F32 {
 };
 
 // 16-bit formats round pairs: a <2 x float> -> <2 x half|bfloat>
-// conversion is one v_cvt_pk_{f16,bf16}_f32.
+// conversion is one v_cvt_pk_{f16,bf16}_f32.  Accesses of TA_HALF_VEC
+// elements: 4 (8 bytes), so that four accesses per thread keep 16 elements
+// in flight in ~70 VGPRs (seven waves per SIMD); 8-element accesses need
+// ~128 VGPRs for the same work and ran 7-12 % slower.
+#ifndef TA_HALF_VEC
+#define TA_HALF_VEC 4
+#endif
 template <class Derived>
 struct Half16 {
   using raw = uint16_t;
   using val = float;
-  static constexpr int kVec = 8;
-  static __device__ void unpack(const u32x4 &w, val *v) {
-    raw h[8];
-    __builtin_memcpy(h, &w, 16);
+  static constexpr int kVec = TA_HALF_VEC;
+  using vec = uint32_t __attribute__((ext_vector_type(kVec / 2)));
+  static __device__ void unpack(const vec &w, val *v) {
+    raw h[kVec];
+    __builtin_memcpy(h, &w, sizeof(vec));
 #pragma unroll
-    for (int e = 0; e < 8; ++e) v[e] = Derived::load(h[e]);
+    for (int e = 0; e < kVec; ++e) v[e] = Derived::load(h[e]);
   }
-  static __device__ u32x4 pack(const val *v) {
-    u32x4 w;
+  static __device__ vec pack(const val *v) {
+    vec w;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) w[j] = Derived::store2(v[2 * j], v[2 * j + 1]);
+    for (int j = 0; j < kVec / 2; ++j)
+      w[j] = Derived::store2(v[2 * j], v[2 * j + 1]);
     return w;
   }
 };
@@ -92,6 +103,7 @@ struct BF16 : Half16<BF16> {
 struct F64 {
   using raw = uint64_t;
   using val = double;
+  using vec = u32x4;
   static constexpr int kVec = 2;
   static __device__ val load(raw v) { return __longlong_as_double(int64_t(v)); }
   static __device__ raw store(val f) { return raw(__double_as_longlong(f)); }
@@ -415,9 +427,11 @@ struct IoPtrs {
 // MI355X (2^27-2^29 elements):
 //   one input, several FP32 or FP64 outputs: 256 threads, one 16-byte access
 //     per stream per thread, nontemporal stores;
-//   one output, or 16-bit storage (VALU-bound): two accesses per thread;
-//   two or more inputs (backward, fused forward+backward): 128 threads, one
-//     access, nontemporal loads and stores.
+//   one FP32/FP64 output: two accesses per thread;
+//   two or more FP32/FP64 inputs (backward, fused forward+backward): 128
+//     threads, one access, nontemporal loads and stores;
+//   16-bit storage (instruction-bound): four 8-byte accesses per thread,
+//     nontemporal loads and stores, 256 threads (128 with two inputs).
 // The TA_SHAPE_* macros exist only to re-time alternatives at build time.
 struct Shape {
   int block, unroll;
@@ -433,26 +447,30 @@ struct Shape {
 #define TA_SHAPE_TWOIN {128, 1, true, true}
 #endif
 #ifndef TA_SHAPE_HALF
-#define TA_SHAPE_HALF {256, 2, false, true}
+#define TA_SHAPE_HALF {256, 4, true, true}
+#endif
+#ifndef TA_SHAPE_HALF_TWOIN
+#define TA_SHAPE_HALF_TWOIN {128, 4, true, true}
 #endif
 
 template <class ST, class Op>
 constexpr Shape shape_for() {
+  if (sizeof(typename ST::raw) == 2)
+    return Op::NIN >= 2 ? Shape TA_SHAPE_HALF_TWOIN : Shape TA_SHAPE_HALF;
   if (Op::NIN >= 2) return Shape TA_SHAPE_TWOIN;
-  if (sizeof(typename ST::raw) == 2) return Shape TA_SHAPE_HALF;
   if (Op::NOUT >= 2) return Shape TA_SHAPE_MULTI;
   return Shape TA_SHAPE_SINGLE;
 }
 
-template <bool NT>
-__device__ inline u32x4 vload(const char *base, int64_t v) {
-  const u32x4 *p = reinterpret_cast<const u32x4 *>(base) + v;
+template <bool NT, class V = u32x4>
+__device__ inline V vload(const char *base, int64_t v) {
+  const V *p = reinterpret_cast<const V *>(base) + v;
   if constexpr (NT) return __builtin_nontemporal_load(p);
   return *p;
 }
-template <bool NT>
-__device__ inline void vstore(char *base, int64_t v, u32x4 x) {
-  u32x4 *p = reinterpret_cast<u32x4 *>(base) + v;
+template <bool NT, class V>
+__device__ inline void vstore(char *base, int64_t v, V x) {
+  V *p = reinterpret_cast<V *>(base) + v;
   if constexpr (NT) {
     __builtin_nontemporal_store(x, p);
   } else {
@@ -500,13 +518,13 @@ __global__ __launch_bounds__(BLOCK, TA_MIN_BLOCKS) void map_vec_kernel(IoPtrs io
 #pragma unroll
   for (int k = 0; k < Op::NOUT; ++k)
     out_base[k] = io.out[k] + head * int64_t(sizeof(raw));
-  u32x4 in_raw[UNROLL][Op::NIN];
+  typename ST::vec in_raw[UNROLL][Op::NIN];
 #pragma unroll
   for (int u = 0; u < UNROLL; ++u) {
     const int64_t v = v0 + int64_t(u) * BLOCK;
     if (v < nvec) {
 #pragma unroll
-      for (int k = 0; k < Op::NIN; ++k) in_raw[u][k] = vload<NTL>(in_base[k], v);
+      for (int k = 0; k < Op::NIN; ++k) in_raw[u][k] = vload<NTL, typename ST::vec>(in_base[k], v);
     }
   }
 #pragma unroll
@@ -584,7 +602,7 @@ __global__ __launch_bounds__(kEncodeBlock) void encode_kernel(
   if (v < nvec) {
     val xf[VEC];
     if constexpr (VEC_PATH) {
-      ST::unpack(vload<false>(x + head * int64_t(sizeof(raw)), v), xf);
+      ST::unpack(vload<false, typename ST::vec>(x + head * int64_t(sizeof(raw)), v), xf);
     } else {
       xf[0] = ST::load(reinterpret_cast<const raw *>(x)[v]);
     }
