@@ -427,9 +427,12 @@ struct IoPtrs {
 // MI355X (2^27-2^29 elements):
 //   one input, several FP32 or FP64 outputs: 256 threads, one 16-byte access
 //     per stream per thread, nontemporal stores;
-//   one FP32/FP64 output: two accesses per thread;
-//   two or more FP32/FP64 inputs (backward, fused forward+backward): 128
-//     threads, one access, nontemporal loads and stores;
+//   one FP32/FP64 output, the method (LDS table): four accesses per thread,
+//     nontemporal loads and stores;
+//   one FP32/FP64 output, light functors (Taylor, copy): one access;
+//   two FP32/FP64 inputs, one output (backward): 128 threads, two accesses,
+//     nontemporal loads and stores; two outputs (fused forward+backward):
+//     one access;
 //   16-bit storage (instruction-bound): four 8-byte accesses per thread,
 //     nontemporal loads and stores, 256 threads (128 with two inputs).
 // The TA_SHAPE_* macros exist only to re-time alternatives at build time.
@@ -441,10 +444,16 @@ struct Shape {
 #define TA_SHAPE_MULTI {256, 1, false, true}
 #endif
 #ifndef TA_SHAPE_SINGLE
-#define TA_SHAPE_SINGLE {256, 2, false, true}
+#define TA_SHAPE_SINGLE {256, 4, true, true}
+#endif
+#ifndef TA_SHAPE_LIGHT
+#define TA_SHAPE_LIGHT {256, 1, false, true}
 #endif
 #ifndef TA_SHAPE_TWOIN
 #define TA_SHAPE_TWOIN {128, 1, true, true}
+#endif
+#ifndef TA_SHAPE_TWOIN1
+#define TA_SHAPE_TWOIN1 {128, 2, true, true}
 #endif
 #ifndef TA_SHAPE_HALF
 #define TA_SHAPE_HALF {256, 4, true, true}
@@ -457,9 +466,11 @@ template <class ST, class Op>
 constexpr Shape shape_for() {
   if (sizeof(typename ST::raw) == 2)
     return Op::NIN >= 2 ? Shape TA_SHAPE_HALF_TWOIN : Shape TA_SHAPE_HALF;
-  if (Op::NIN >= 2) return Shape TA_SHAPE_TWOIN;
+  if (Op::NIN >= 2)
+    return Op::NOUT == 1 ? Shape TA_SHAPE_TWOIN1 : Shape TA_SHAPE_TWOIN;
   if (Op::NOUT >= 2) return Shape TA_SHAPE_MULTI;
-  return Shape TA_SHAPE_SINGLE;
+  // the functors that evaluate the method use the LDS table
+  return Op::Table::kUsed ? Shape TA_SHAPE_SINGLE : Shape TA_SHAPE_LIGHT;
 }
 
 template <bool NT, class V = u32x4>
