@@ -79,7 +79,8 @@ __host__ __device__ constexpr double kdet_of_row(int idx) {
 }
 
 // Per-workgroup copy of the table in LDS (no table in HBM).  Rows are
-// indexed j + 4*(q & 1): rows 0-2 even quadrants, 4-6 odd, 3 and 7 unused.
+// indexed j + 4*(q & 1): rows 0-2 even quadrants, 4-6 odd; rows 3 and 7
+// repeat rows 2 and 6 for t = 45 degrees exactly (slot 3, see slot_of).
 // One lane writes it with immediates; the caller synchronises.
 struct Tables {
   PieceRow row[8];
@@ -95,9 +96,12 @@ struct Tables {
         tb.kdet64[slot] = kdet_of_row(i);
         tb.kdet[slot] = float(kdet_of_row(i));
       }
-      tb.row[3] = tb.row[7] = PieceRow{0.0, 0.0, 1.0, 0.0};
-      tb.kdet64[3] = tb.kdet64[7] = 0.0;
-      tb.kdet[3] = tb.kdet[7] = 0.0f;
+      tb.row[3] = tb.row[2];
+      tb.row[7] = tb.row[6];
+      tb.kdet64[3] = tb.kdet64[2];
+      tb.kdet64[7] = tb.kdet64[6];
+      tb.kdet[3] = tb.kdet[2];
+      tb.kdet[7] = tb.kdet[6];
     }
   }
 };
@@ -167,7 +171,8 @@ __device__ inline void reduce(float x, double &r, uint32_t &q) {
   // q = round(x 2/pi) by adding 1.5 2^52 (the product is rounded first: an
   // x within an ulp of a half-integer multiple of pi/4 may get the other
   // neighbour and |r| up to pi/4 (1 + 2^-50), where pieces 2 and 3 meet
-  // continuously)
+  // continuously).  A single FMA would need the 64-bit constant copied into
+  // its accumulator register first: no fewer instructions.
   const double qb = xd * kTwoOverPi + kRoundMagic;
   const double qd = qb - kRoundMagic;  // +0 when q = 0, so r keeps x's zero
   q = uint32_t(__double2loint(qb));    // low word of the mantissa = q
@@ -178,6 +183,14 @@ __device__ inline void reduce(float x, double &r, uint32_t &q) {
 
 // Folded element: everything the later stages need.
 constexpr double kPi12 = 0x1.0c152382d7366p-2;  // RN(pi/12)
+
+// 15-degree slot of t in [0, 45(1 + 2^-50)] degrees: floor(t/15) by a
+// truncating conversion; t = 45 gives slot 3, whose table row repeats slot
+// 2.  Within an ulp of 15 or 30 the product may round across the node (the
+// pieces' jump: either side is accepted there).  NaN converts to 0.
+__device__ inline uint32_t slot_of(double t) {
+  return uint32_t(t * (1.0 / 15.0));
+}
 
 struct Folded {
   double r;       // reduced argument, |r| <= pi/4 (use abs_r())
@@ -194,7 +207,7 @@ __device__ inline Folded fold(float x) {
   f.hr = uint32_t(__double2hiint(f.r));
   f.t = f.abs_r() * kDegPerRad;  // the abs folds into the multiply
   // j = 15-degree slot of |r|; the family (q & 1) selects slots 4..6
-  const uint32_t j = f.t >= 30.0 ? 2u : (f.t >= 15.0 ? 1u : 0u);
+  const uint32_t j = slot_of(f.t);
   f.row = ((f.q << 2) & 4u) | j;
   return f;
 }
@@ -502,8 +515,7 @@ __device__ inline Folded64 fold64(double x) {
   const double ra = f.abs_r();
   f.t = __builtin_fma(ra, kDegPerRad,
                       __builtin_fma(ra, kDegPerRadLo, f.abs_rl() * kDegPerRad));
-  const uint32_t j = f.t >= 30.0 ? 2u : (f.t >= 15.0 ? 1u : 0u);
-  f.row = ((f.q << 2) & 4u) | j;
+  f.row = ((f.q << 2) & 4u) | slot_of(f.t);
   return f;
 }
 
