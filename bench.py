@@ -129,6 +129,19 @@ def main():
     per, total, wall = time_launches(step, args.steps, args.warmup, torch)
     ms_per_step = total / args.steps
     kernel_ms = sum(per) / len(per)
+    pq = sorted(per)
+
+    def pct(p):
+        return round(pq[min(len(pq) - 1, int(p * len(pq)))], 5)
+
+    # the achievable ceiling for this byte mix: a copy of 1 read -> 3 writes
+    # with the same access pattern, timed the same way
+    log("timing copy 1 -> 3 (ceiling)")
+    cper, _, _ = time_launches(lambda: ta.ta_copy([x], [ys, yc, yt]),
+                               args.steps, args.warmup, torch)
+    copy_gbs = 16 * n / (sum(cper) / len(cper) * 1e-3) / 1e9
+    step()
+    torch.cuda.synchronize()
     gelem = n / (ms_per_step * 1e-3) / 1e9
     alg_bytes = 16 * n
     achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
@@ -159,9 +172,15 @@ def main():
             "traffic": traffic,
             "kernel": "map_vec_kernel<F32, FwdOp<sin|cos|tan>>",
             "kernel_ms": round(kernel_ms, 5),
+            "kernel_ms_p10_p50_p90": [pct(0.1), pct(0.5), pct(0.9)],
             "algorithmic_bytes_per_launch": alg_bytes,
+            "copy_1in_3out_gbs": round(copy_gbs, 1),
+            "frac_of_copy": round(achieved / copy_gbs, 4),
         },
     }
+    if traffic:
+        out["roofline"]["traffic_gbs"] = round(
+            traffic / (kernel_ms * 1e-3) / 1e9, 1)
     valu = sq_per_elem().get("sincos_tan_f32")
     if valu:
         lane = valu * n / (kernel_ms * 1e-3)
@@ -198,10 +217,26 @@ def cpu_baseline(x_host, seconds):
     t0 = time.perf_counter()
     r = oracle.forward(sample, nthreads=threads)
     dt = time.perf_counter() - t0
+    m1 = 1 << 22
+    t0 = time.perf_counter()
+    oracle.forward(x_host[:m1].astype(np.float64), nthreads=1)
+    dt1 = time.perf_counter() - t0
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": round(m / dt / 1e9, 5), "unit": "Gelem/s",
             "cores": int(r["threads"]), "kind": "oracle",
             "sample": f"first {m} elements of the 2^28 workload, "
-                      f"sin+cos+tan, {dt:.1f} s"}
+                      f"sin+cos+tan, {dt:.1f} s",
+            "one_core": {"value": round(m1 / dt1 / 1e9, 5),
+                         "sample": f"first {m1} elements, {dt1:.1f} s"},
+            "cpu_model": model, "host_cpus": os.cpu_count()}
 
 
 def comparators(x, x_host, n, args, torch, ta, np):
