@@ -164,3 +164,16 @@ def test_binding_refuses_cpu_tensors():
             fn(x)
     with pytest.raises(ta.TaError):
         ta.SinFn.apply(x)
+
+
+def test_c_example_links_against_the_header_and_library():
+    """tests/c_abi/ta_example is plain C (C99, -Werror) compiled against
+    include/ta.h and linked to libta.so; without arguments it prints its
+    usage and exits 2 before any HIP call."""
+    import subprocess
+    exe = os.path.join(ROOT, "tests", "c_abi", "ta_example")
+    if not os.path.exists(exe):
+        pytest.fail("tests/c_abi/ta_example is not built "
+                    "(run __graft_entry__.build())")
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 2 and "usage" in r.stderr
