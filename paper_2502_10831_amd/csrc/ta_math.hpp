@@ -81,9 +81,16 @@ __host__ __device__ constexpr double kdet_of_row(int idx) {
 // Per-workgroup copy of the table in LDS (no table in HBM).  Rows are
 // indexed j + 4*(q & 1): rows 0-2 even quadrants, 4-6 odd; rows 3 and 7
 // repeat rows 2 and 6 for t = 45 degrees exactly (slot 3, see slot_of).
+// Stored as two arrays of 16-byte (intercept, slope) pairs, for N and for
+// D: the eight rows of one array then fill 32 distinct LDS banks, so a
+// wave reading rows of both quadrant families has no bank conflict (rows
+// of 32 bytes put rows j and j + 4 on the same banks).
 // One lane writes it with immediates; the caller synchronises.
+struct Lin {
+  double i, s;  // value = i + s t
+};
 struct Tables {
-  PieceRow row[8];
+  Lin n[8], d[8];
   double kdet64[8];  // FP64 path
   float kdet[8];
   static constexpr bool kUsed = true;
@@ -92,12 +99,16 @@ struct Tables {
 #pragma unroll
       for (int i = 0; i < 6; ++i) {
         const int slot = i < 3 ? i : i + 1;
-        tb.row[slot] = piece_row(i);
+        const PieceRow r = piece_row(i);
+        tb.n[slot] = Lin{r.iN, r.sN};
+        tb.d[slot] = Lin{r.iD, r.sD};
         tb.kdet64[slot] = kdet_of_row(i);
         tb.kdet[slot] = float(kdet_of_row(i));
       }
-      tb.row[3] = tb.row[2];
-      tb.row[7] = tb.row[6];
+      tb.n[3] = tb.n[2];
+      tb.n[7] = tb.n[6];
+      tb.d[3] = tb.d[2];
+      tb.d[7] = tb.d[6];
       tb.kdet64[3] = tb.kdet64[2];
       tb.kdet64[7] = tb.kdet64[6];
       tb.kdet[3] = tb.kdet[2];
@@ -248,9 +259,9 @@ struct Forms {
 };
 
 __device__ inline Forms forms(const Folded &f, const Tables &tb) {
-  const PieceRow c = tb.row[f.row];
-  const double nd = __builtin_fma(c.sN, f.t, c.iN);
-  const double dd = __builtin_fma(c.sD, f.t, c.iD);
+  const Lin a = tb.n[f.row], b = tb.d[f.row];
+  const double nd = __builtin_fma(a.s, f.t, a.i);
+  const double dd = __builtin_fma(b.s, f.t, b.i);
   const double qd = __builtin_fma(nd, nd, dd * dd);
   return Forms{float(nd), float(dd), float(qd)};
 }
@@ -523,9 +534,9 @@ struct Forms64 {
   double n, d, q;
 };
 __device__ inline Forms64 forms64(const Folded64 &f, const Tables &tb) {
-  const PieceRow c = tb.row[f.row];
-  const double nd = __builtin_fma(c.sN, f.t, c.iN);
-  const double dd = __builtin_fma(c.sD, f.t, c.iD);
+  const Lin a = tb.n[f.row], b = tb.d[f.row];
+  const double nd = __builtin_fma(a.s, f.t, a.i);
+  const double dd = __builtin_fma(b.s, f.t, b.i);
   return Forms64{nd, dd, __builtin_fma(nd, nd, dd * dd)};
 }
 
