@@ -705,7 +705,7 @@ def summarize(a):
             d = per.setdefault(key, {}).setdefault(r["Counter_Name"], {})
             disp = r.get("Dispatch_Id") or r.get("Correlation_Id")
             d[disp] = d.get(disp, 0.0) + float(r["Counter_Value"])
-        lines = ["# rocprofv3 --pmc SQ instruction counters (per dispatch)",
+        lines = ["# rocprofv3 --pmc SQ counters (per dispatch)",
                  f"# command: {cmd}", f"source_sha: {source_hash()}",
                  "# per_elem = wave instructions * 64 lanes / elements"]
         for key, counters in sorted(per.items()):

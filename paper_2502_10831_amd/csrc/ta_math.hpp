@@ -623,11 +623,14 @@ __device__ inline double fisr(double number) {
 // quadratic x a^2 + ..: qx = a^2 + c^2, qy = 2(ab + cd), qz = b^2 + d^2
 // (Appendix A.4), evaluated in that order.
 struct PaperRow {
-  double a, b, c, d, qx, qy, qz, pad;
+  double a, b, c, d, qx, qy, qz;
 };
 
+// In LDS as four arrays of 16-byte pairs, (a, b), (c, d), (qx, qy),
+// (qz, 0), eight rows each: a wave reading different pieces hits distinct
+// banks (rows of 64 bytes would put pieces k and k + 2 on the same banks).
 struct PaperTables {
-  PaperRow row[6];
+  Lin ab[8], cd[8], qxy[8], qz0[8];
   static constexpr bool kUsed = true;
   __device__ static void init(PaperTables &tb) {
     if (threadIdx.x == 0) {
@@ -641,10 +644,16 @@ struct PaperTables {
         r.qx = r.a * r.a + r.c * r.c;
         r.qy = 2.0 * (r.a * r.b + r.c * r.d);
         r.qz = r.b * r.b + r.d * r.d;
-        r.pad = 0.0;
-        tb.row[k] = r;
+        tb.ab[k] = Lin{r.a, r.b};
+        tb.cd[k] = Lin{r.c, r.d};
+        tb.qxy[k] = Lin{r.qx, r.qy};
+        tb.qz0[k] = Lin{r.qz, 0.0};
       }
     }
+  }
+  __device__ PaperRow row(int k) const {
+    return PaperRow{ab[k].i, ab[k].s, cd[k].i, cd[k].s, qxy[k].i, qxy[k].s,
+                    qz0[k].i};
   }
 };
 
@@ -654,7 +663,7 @@ __device__ inline void paper_eval(double ang, double divisor,
                                   double &t) {
   int k = int(ang / divisor);
   k = k > 5 ? 5 : k;
-  const PaperRow r = tb.row[k];
+  const PaperRow r = tb.row(k);
   const double poly_s = r.a * ang + r.b;             // Algorithm 2: poly
   const double ang2 = ang * ang;                     // Algorithm 2: ang2
   const double inner = r.qx * ang2 + r.qy * ang + r.qz;
