@@ -327,6 +327,17 @@ def comparators(x, x_host, n, args, torch, ta, np):
     ms = total / args.steps
     res["copy_1in_3out_ceiling"] = {"gbs": round(16 * n / (ms * 1e-3) / 1e9, 1),
                                     "ms": round(ms, 5)}
+
+    # context for that ceiling: writes alone (torch's fill kernel on the
+    # same three arrays)
+    def fills():
+        ys.fill_(1.0)
+        yc.fill_(2.0)
+        yt.fill_(3.0)
+    per, total, _ = time_launches(fills, max(5, args.steps // 4), 3, torch)
+    ms = total / max(5, args.steps // 4)
+    res["torch_fill_3_arrays_write_only"] = {
+        "gbs": round(12 * n / (ms * 1e-3) / 1e9, 1)}
     return res
 
 
