@@ -79,13 +79,13 @@ enum {
 
 /* ---- forward: the proposed functions (Section 2 formulas, Section 3 fold) */
 
-/* y[i] = sin_a(x[i]).  Section 2 "Sine Function" cases. */
+/* y[i] = sin_a(x[i]).  Section 2, sine cases. */
 ta_status ta_sin(const void *x, void *y, int64_t n, ta_dtype dt,
                  hipStream_t stream);
-/* y[i] = cos_a(x[i]).  Section 2 "Cosine Function" cases. */
+/* y[i] = cos_a(x[i]).  Section 2, cosine cases. */
 ta_status ta_cos(const void *x, void *y, int64_t n, ta_dtype dt,
                  hipStream_t stream);
-/* y[i] = tan_a(x[i]).  Section 2 "Tangent Function" cases; finite up to the
+/* y[i] = tan_a(x[i]).  Section 2, tangent cases; finite up to the
  * pole (the last piece's D vanishes only at exactly pi/2). */
 ta_status ta_tan(const void *x, void *y, int64_t n, ta_dtype dt,
                  hipStream_t stream);
@@ -100,7 +100,7 @@ ta_status ta_tan_ex(const void *x, void *y, int64_t n, ta_dtype dt,
 ta_status ta_sincos_ex(const void *x, void *ys, void *yc, void *yt, int64_t n,
                        ta_dtype dt, uint32_t flags, hipStream_t stream);
 
-/* ---- Taylor baseline (Section 3 "Taylor series"; Tables 1-3 columns) ----
+/* ---- Taylor baseline (Section 3, Taylor comparison; Tables 1-3 columns) ----
  * The first `terms` (5, 7 or 9) non-zero Maclaurin terms of sin, cos or tan,
  * in FP32 Horner form, evaluated on the same folded angle rho in [0, pi/2]
  * with the same signs.  terms outside {5, 7, 9} -> TA_EINVAL. */

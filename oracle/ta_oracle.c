@@ -17,7 +17,7 @@
  *      decimals and says full precision was used.  Appendix A (eqs. 5-10)
  *      gives every segment as tan t = (a t + b)/(c t + d) with small integer
  *      a, b, c, d and t in degrees.  The radian coefficients are a*180/pi and
- *      c*180/pi with b, d unchanged, so "full precision" is the integer form
+ *      c*180/pi with b, d unchanged, so the unrounded coefficients are the integer form
  *      with t = rho*180/pi.  (The tests check that truncating these values to
  *      two decimals gives all 42 numbers printed in Section 2.)
  *  R2  Reduction.  Section 3 reduces the angle to [0, pi/2] "along with the
@@ -60,7 +60,7 @@ static const double OR_B[6] = {0.0, 10.0, 46.0, 217.0, 297.0, 542.0};
 static const double OR_C[6] = {-1.0, -4.0, -5.0, -13.0, -10.0, -11.0};
 static const double OR_D[6] = {632.0, 657.0, 541.0, 1252.0, 910.0, 990.0};
 
-/* Degrees per radian in double ("full precision", reading R1). */
+/* Degrees per radian in double (the unrounded coefficients, reading R1). */
 static double or_k(void) { return 180.0 / M_PI; }
 
 /* ---- reduction (Section 3, reading R2) ---------------------------------- */
