@@ -128,10 +128,10 @@ struct F64 {
 enum : int { kSin = 1, kCos = 2, kTan = 4 };
 
 // LOW: the variant for 16-bit storage.  Its outputs keep 8 (BF16) or 11
-// (FP16) significant bits, so the hardware inverse square root and
-// reciprocal (each within about one FP32 ulp) are used without the Newton
-// refinement; the result stays within the FP32 tolerance before the 16-bit
-// rounding.  Every op names the instance the 16-bit formats launch (Low).
+// (FP16) significant bits, so the whole evaluation runs in FP32
+// (fold_forms16) and the hardware inverse square root and reciprocal (each
+// within about one FP32 ulp) are used without the Newton refinement.
+// Every op names the instance the 16-bit formats launch (Low).
 template <int MASK, bool GUARD, bool LOW = false>
 struct FwdOp {
   static constexpr int NIN = 1;
@@ -141,8 +141,17 @@ struct FwdOp {
   using Low = FwdOp<MASK, GUARD, true>;
   __device__ static void apply(const float *in, float *out, const Table &tb,
                                   uint32_t) {
-    const Folded f = fold(in[0]);
-    const Forms v = forms(f, tb);
+    if constexpr (LOW) {
+      FoldedL f;
+      const Forms v = fold_forms16(in[0], tb, f);
+      finish(f, v, out);
+    } else {
+      const Folded f = fold(in[0]);
+      finish(f, forms(f, tb), out);
+    }
+  }
+  template <class F>
+  __device__ static void finish(const F &f, const Forms &v, float *out) {
     int o = 0;
     if constexpr ((MASK & (kSin | kCos)) != 0) {
       const float y = LOW ? rsqrt_est(v.q) : rsqrt_refined(v.q);
@@ -221,8 +230,18 @@ struct BwdOp {
   using Low = BwdOp<WHICH, WITH_Y, true>;
   __device__ static void apply(const float *in, float *out, const Table &tb,
                                   uint32_t) {
-    const Folded f = fold(in[0]);
-    const Forms v = forms(f, tb);
+    if constexpr (LOW) {
+      FoldedL f;
+      const Forms v = fold_forms16(in[0], tb, f);
+      finish(f, v, in, out, tb);
+    } else {
+      const Folded f = fold(in[0]);
+      finish(f, forms(f, tb), in, out, tb);
+    }
+  }
+  template <class F>
+  __device__ static void finish(const F &f, const Forms &v, const float *in,
+                                float *out, const Table &tb) {
     const float kdet = tb.kdet[f.row];
     if constexpr (WHICH == kTan) {
       const float r = LOW ? rcp_est(v.d) : rcp_refined(v.d);
@@ -282,8 +301,18 @@ struct SinCosBwdOp {
   using Low = SinCosBwdOp<HAS_GS, HAS_GC, true>;
   __device__ static void apply(const float *in, float *out, const Table &tb,
                                   uint32_t) {
-    const Folded f = fold(in[0]);
-    const Forms v = forms(f, tb);
+    if constexpr (LOW) {
+      FoldedL f;
+      const Forms v = fold_forms16(in[0], tb, f);
+      finish(f, v, in, out, tb);
+    } else {
+      const Folded f = fold(in[0]);
+      finish(f, forms(f, tb), in, out, tb);
+    }
+  }
+  template <class F>
+  __device__ static void finish(const F &f, const Forms &v, const float *in,
+                                float *out, const Table &tb) {
     const float y = LOW ? rsqrt_est(v.q) : rsqrt_refined(v.q);
     const float omega = tb.kdet[f.row] * y * y;
     float acc = 0.0f;

@@ -49,23 +49,25 @@ constexpr int kB[6] = {0, 10, 46, 217, 297, 542};
 constexpr int kC[6] = {-1, -4, -5, -13, -10, -11};
 constexpr int kD[6] = {632, 657, 541, 1252, 910, 990};
 
-// Logical row idx = j + 3*(q & 1) of the per-element coefficient table (kept
-// in LDS slot j + 4*(q & 1)), where j is
-// the 15-degree slot of a = |r| in [0, 45] degrees.  q even: rho = a, piece
-// k = j, N = b + a_k t, D = d + c_k t.  q odd: rho = 90 - a, piece k = 5 - j,
-// and with t = a (the complement) N = (90 a_k + b_k) - a_k t and
-// D = (90 c_k + d_k) - c_k t.
+// Row r = j + 4*(q & 1) of the per-element coefficient table, where j is
+// the 15-degree slot of a = |r| in degrees (0-2 on [0, 45]; 3 just above
+// 45, reached when q is the neighbour of the nearest quadrant).  q even:
+// rho = a, piece k = j, N = b + a_k t, D = d + c_k t with t = a.  q odd:
+// rho = 90 - a, piece k = 5 - j, and with t = a (the complement)
+// N = (90 a_k + b_k) - a_k t and D = (90 c_k + d_k) - c_k t.  The fold, the
+// signs and these forms hold for any |r| < pi/2, so slot 3 (piece 3, or
+// piece 2 about 90 degrees) continues both families exactly.
 struct PieceRow {
   double iN, sN, iD, sD;  // N = iN + sN t, D = iD + sD t (t in degrees)
 };
 
 __host__ __device__ constexpr int piece_of_row(int idx) {
-  return idx < 3 ? idx : 5 - (idx - 3);
+  return idx < 4 ? idx : 5 - (idx - 4);
 }
 
 __host__ __device__ constexpr PieceRow piece_row(int idx) {
   const int k = piece_of_row(idx);
-  return idx < 3 ? PieceRow{double(kB[k]), double(kA[k]), double(kD[k]),
+  return idx < 4 ? PieceRow{double(kB[k]), double(kA[k]), double(kD[k]),
                             double(kC[k])}
                  : PieceRow{double(90 * kA[k] + kB[k]), double(-kA[k]),
                             double(90 * kC[k] + kD[k]), double(-kC[k])};
@@ -78,41 +80,36 @@ __host__ __device__ constexpr double kdet_of_row(int idx) {
   return kDegPerRad * double(kA[k] * kD[k] - kB[k] * kC[k]);
 }
 
-// Per-workgroup copy of the table in LDS (no table in HBM).  Rows are
-// indexed j + 4*(q & 1): rows 0-2 even quadrants, 4-6 odd; rows 3 and 7
-// repeat rows 2 and 6 for t = 45 degrees exactly (slot 3, see slot_of).
-// Stored as two arrays of 16-byte (intercept, slope) pairs, for N and for
-// D: the eight rows of one array then fill 32 distinct LDS banks, so a
-// wave reading rows of both quadrant families has no bank conflict (rows
-// of 32 bytes put rows j and j + 4 on the same banks).
+// Per-workgroup copy of the table in LDS (no table in HBM), rows indexed
+// j + 4*(q & 1).  Stored as two arrays of 16-byte (intercept, slope) pairs,
+// for N and for D: the eight rows of one array then fill 32 distinct LDS
+// banks, so a wave reading rows of both quadrant families has no bank
+// conflict (rows of 32 bytes put rows j and j + 4 on the same banks).  The
+// FP32 copy for 16-bit storage is one 16-byte row per piece.
 // One lane writes it with immediates; the caller synchronises.
 struct Lin {
   double i, s;  // value = i + s t
+};
+struct LinF {
+  float iN, sN, iD, sD;
 };
 struct Tables {
   Lin n[8], d[8];
   double kdet64[8];  // FP64 path
   float kdet[8];
+  LinF f[8];         // 16-bit storage
   static constexpr bool kUsed = true;
   __device__ static void init(Tables &tb) {
     if (threadIdx.x == 0) {
 #pragma unroll
-      for (int i = 0; i < 6; ++i) {
-        const int slot = i < 3 ? i : i + 1;
+      for (int i = 0; i < 8; ++i) {
         const PieceRow r = piece_row(i);
-        tb.n[slot] = Lin{r.iN, r.sN};
-        tb.d[slot] = Lin{r.iD, r.sD};
-        tb.kdet64[slot] = kdet_of_row(i);
-        tb.kdet[slot] = float(kdet_of_row(i));
+        tb.n[i] = Lin{r.iN, r.sN};
+        tb.d[i] = Lin{r.iD, r.sD};
+        tb.kdet64[i] = kdet_of_row(i);
+        tb.kdet[i] = float(kdet_of_row(i));
+        tb.f[i] = LinF{float(r.iN), float(r.sN), float(r.iD), float(r.sD)};
       }
-      tb.n[3] = tb.n[2];
-      tb.n[7] = tb.n[6];
-      tb.d[3] = tb.d[2];
-      tb.d[7] = tb.d[6];
-      tb.kdet64[3] = tb.kdet64[2];
-      tb.kdet64[7] = tb.kdet64[6];
-      tb.kdet[3] = tb.kdet[2];
-      tb.kdet[7] = tb.kdet[6];
     }
   }
 };
@@ -195,10 +192,11 @@ __device__ inline void reduce(float x, double &r, uint32_t &q) {
 // Folded element: everything the later stages need.
 constexpr double kPi12 = 0x1.0c152382d7366p-2;  // RN(pi/12)
 
-// 15-degree slot of t in [0, 45(1 + 2^-50)] degrees: floor(t/15) by a
-// truncating conversion; t = 45 gives slot 3, whose table row repeats slot
-// 2.  Within an ulp of 15 or 30 the product may round across the node (the
-// pieces' jump: either side is accepted there).  NaN converts to 0.
+// 15-degree slot of t in [0, 60) degrees: floor(t/15) by a truncating
+// conversion (t at or just above 45 gives slot 3, the continuation of both
+// families).  Within an ulp of 15 or 30 the product may round across the
+// node (the pieces' jump: either side is accepted there).  NaN converts to
+// 0.
 __device__ inline uint32_t slot_of(double t) {
   return uint32_t(t * (1.0 / 15.0));
 }
@@ -264,6 +262,56 @@ __device__ inline Forms forms(const Folded &f, const Tables &tb) {
   const double dd = __builtin_fma(b.s, f.t, b.i);
   const double qd = __builtin_fma(nd, nd, dd * dd);
   return Forms{float(nd), float(dd), float(qd)};
+}
+
+// ---------------------------------------------------------------------------
+// 16-bit storage: the whole evaluation in FP32 (outputs keep 8 or 11 bits).
+// For |x| < 2^16 (every FP16 value, BF16 below 65536): q = rint(x RN(2/pi))
+// and a three-word Cody-Waite r = x - q pi/2 (the first step exact: x and
+// q C1 are multiples of 2^-23 there and |r| < 1), relative error ~2^-23.
+// The rounded product can put q on the neighbour of the nearest quadrant
+// near odd multiples of pi/4, leaving |r| up to ~0.8: slot 3 of the table
+// continues both families, so that costs nothing.  Larger BF16 values take
+// the FP64 fold.  Then t = |r| 180/pi, N, D, Q by FP32 FMAs from the FP32
+// table row.
+// ---------------------------------------------------------------------------
+constexpr float kTwoOverPiF = 0x1.45f306p-1f;  // RN24(2/pi)
+constexpr float kPio2F1 = 0x1.921fb6p+0f;      // RN24(pi/2)
+constexpr float kPio2F2 = -0x1.777a5cp-25f;    // RN24(pi/2 - F1)
+constexpr float kPio2F3 = -0x1.ee59dap-50f;    // RN24(pi/2 - F1 - F2)
+constexpr float kDegPerRadF = 0x1.ca5dc2p+5f;  // RN24(180/pi)
+constexpr float kSmall16 = 0x1p16f;
+
+struct FoldedL {
+  uint32_t q;    // quadrant, low bits
+  uint32_t hr;   // bit 31 = sign of r
+  uint32_t row;  // table row j + 4*(q & 1)
+  float ar;      // |r|
+  __device__ float abs_r() const { return ar; }
+};
+
+__device__ inline Forms fold_forms16(float x, const Tables &tb, FoldedL &f) {
+  if (__builtin_expect(__builtin_fabsf(x) < kSmall16, 1)) {
+    const float qf = __builtin_rintf(x * kTwoOverPiF);
+    float r = __builtin_fmaf(-qf, kPio2F1, x);
+    r = __builtin_fmaf(-qf, kPio2F2, r);
+    r = __builtin_fmaf(-qf, kPio2F3, r);
+    f.q = uint32_t(int32_t(qf));
+    f.hr = __float_as_uint(r);
+    f.ar = __builtin_fabsf(r);
+    const float t = f.ar * kDegPerRadF;
+    f.row = ((f.q << 2) & 4u) | uint32_t(t * (1.0f / 15.0f));
+    const LinF c = tb.f[f.row];
+    const float n = __builtin_fmaf(c.sN, t, c.iN);
+    const float d = __builtin_fmaf(c.sD, t, c.iD);
+    return Forms{n, d, __builtin_fmaf(n, n, d * d)};
+  }
+  const Folded g = fold(x);  // |x| >= 2^16 (BF16), +-Inf, NaN
+  f.q = g.q;
+  f.hr = g.hr;
+  f.row = g.row;
+  f.ar = float(g.abs_r());
+  return forms(g, tb);
 }
 
 // ---------------------------------------------------------------------------
