@@ -34,11 +34,14 @@ def log(msg):
 
 
 def source_hash() -> str:
+    """Hash of the kernel sources and the header they compile against."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2502_10831_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, name), "rb") as f:
-            h.update(name.encode())
+    paths = [os.path.join(csrc, name) for name in sorted(os.listdir(csrc))]
+    paths.append(os.path.join(ROOT, "include", "ta.h"))
+    for path in paths:
+        with open(path, "rb") as f:
+            h.update(os.path.basename(path).encode())
             h.update(f.read())
     return h.hexdigest()[:16]
 

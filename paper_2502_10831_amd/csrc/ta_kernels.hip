@@ -13,6 +13,8 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <type_traits>
+
 #include "ta.h"
 #include "ta_math.hpp"
 
@@ -137,7 +139,7 @@ struct FwdOp {
   static constexpr int NIN = 1;
   static constexpr int NOUT = ((MASK & kSin) ? 1 : 0) + ((MASK & kCos) ? 1 : 0) +
                               ((MASK & kTan) ? 1 : 0);
-  using Table = Tables;
+  using Table = typename std::conditional<LOW, Tables16, TablesFwd>::type;
   using Low = FwdOp<MASK, GUARD, true>;
   __device__ static void apply(const float *in, float *out, const Table &tb,
                                   uint32_t) {
@@ -226,7 +228,7 @@ template <int WHICH, bool WITH_Y, bool LOW = false>
 struct BwdOp {
   static constexpr int NIN = 2;  // x, gy
   static constexpr int NOUT = WITH_Y ? 2 : 1;
-  using Table = Tables;
+  using Table = typename std::conditional<LOW, Tables16, TablesBwd>::type;
   using Low = BwdOp<WHICH, WITH_Y, true>;
   __device__ static void apply(const float *in, float *out, const Table &tb,
                                   uint32_t) {
@@ -297,7 +299,7 @@ template <bool HAS_GS, bool HAS_GC, bool LOW = false>
 struct SinCosBwdOp {
   static constexpr int NIN = 1 + (HAS_GS ? 1 : 0) + (HAS_GC ? 1 : 0);
   static constexpr int NOUT = 1;
-  using Table = Tables;
+  using Table = typename std::conditional<LOW, Tables16, TablesBwd>::type;
   using Low = SinCosBwdOp<HAS_GS, HAS_GC, true>;
   __device__ static void apply(const float *in, float *out, const Table &tb,
                                   uint32_t) {
@@ -634,8 +636,8 @@ __global__ __launch_bounds__(kEncodeBlock) void encode_kernel(
   using val = typename ST::val;
   using Core = FwdOp<kSin | kCos, false, sizeof(raw) == 2>;
   constexpr int VEC = VEC_PATH ? ST::kVec : 1;
-  __shared__ Tables tb;
-  Tables::init(tb);
+  __shared__ typename Core::Table tb;
+  Core::Table::init(tb);
   __syncthreads();
   const int64_t plane = n * int64_t(sizeof(raw));
   const int64_t v = int64_t(blockIdx.x) * kEncodeBlock + threadIdx.x;

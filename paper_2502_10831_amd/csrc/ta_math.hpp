@@ -93,22 +93,50 @@ struct Lin {
 struct LinF {
   float iN, sN, iD, sD;
 };
-struct Tables {
+
+// Each kernel family writes only the arrays it reads: the forward (FP32 and
+// FP64 storage) the N and D pairs, the backward also the derivative factors,
+// the 16-bit kernels the FP32 rows and the FP32 factors.
+struct TablesFwd {
   Lin n[8], d[8];
-  double kdet64[8];  // FP64 path
-  float kdet[8];
-  LinF f[8];         // 16-bit storage
   static constexpr bool kUsed = true;
-  __device__ static void init(Tables &tb) {
+  __device__ static void fill(TablesFwd &tb) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const PieceRow r = piece_row(i);
+      tb.n[i] = Lin{r.iN, r.sN};
+      tb.d[i] = Lin{r.iD, r.sD};
+    }
+  }
+  __device__ static void init(TablesFwd &tb) {
+    if (threadIdx.x == 0) fill(tb);
+  }
+};
+struct TablesBwd : TablesFwd {
+  double kdet64[8];  // FP64 storage
+  float kdet[8];
+  __device__ static void init(TablesBwd &tb) {
+    if (threadIdx.x == 0) {
+      fill(tb);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        tb.kdet64[i] = kdet_of_row(i);
+        tb.kdet[i] = float(kdet_of_row(i));
+      }
+    }
+  }
+};
+struct Tables16 {
+  LinF f[8];
+  float kdet[8];
+  static constexpr bool kUsed = true;
+  __device__ static void init(Tables16 &tb) {
     if (threadIdx.x == 0) {
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
         const PieceRow r = piece_row(i);
-        tb.n[i] = Lin{r.iN, r.sN};
-        tb.d[i] = Lin{r.iD, r.sD};
-        tb.kdet64[i] = kdet_of_row(i);
-        tb.kdet[i] = float(kdet_of_row(i));
         tb.f[i] = LinF{float(r.iN), float(r.sN), float(r.iD), float(r.sD)};
+        tb.kdet[i] = float(kdet_of_row(i));
       }
     }
   }
@@ -256,7 +284,7 @@ struct Forms {
   float n, d, q;  // N, D and Q = N^2 + D^2, each rounded once from FP64
 };
 
-__device__ inline Forms forms(const Folded &f, const Tables &tb) {
+__device__ inline Forms forms(const Folded &f, const TablesFwd &tb) {
   const Lin a = tb.n[f.row], b = tb.d[f.row];
   const double nd = __builtin_fma(a.s, f.t, a.i);
   const double dd = __builtin_fma(b.s, f.t, b.i);
@@ -290,7 +318,8 @@ struct FoldedL {
   __device__ float abs_r() const { return ar; }
 };
 
-__device__ inline Forms fold_forms16(float x, const Tables &tb, FoldedL &f) {
+__device__ inline Forms fold_forms16(float x, const Tables16 &tb, FoldedL &f) {
+  float t;
   if (__builtin_expect(__builtin_fabsf(x) < kSmall16, 1)) {
     const float qf = __builtin_rintf(x * kTwoOverPiF);
     float r = __builtin_fmaf(-qf, kPio2F1, x);
@@ -299,19 +328,20 @@ __device__ inline Forms fold_forms16(float x, const Tables &tb, FoldedL &f) {
     f.q = uint32_t(int32_t(qf));
     f.hr = __float_as_uint(r);
     f.ar = __builtin_fabsf(r);
-    const float t = f.ar * kDegPerRadF;
+    t = f.ar * kDegPerRadF;
     f.row = ((f.q << 2) & 4u) | uint32_t(t * (1.0f / 15.0f));
-    const LinF c = tb.f[f.row];
-    const float n = __builtin_fmaf(c.sN, t, c.iN);
-    const float d = __builtin_fmaf(c.sD, t, c.iD);
-    return Forms{n, d, __builtin_fmaf(n, n, d * d)};
+  } else {
+    const Folded g = fold(x);  // |x| >= 2^16 (BF16), +-Inf, NaN
+    f.q = g.q;
+    f.hr = g.hr;
+    f.row = g.row;
+    f.ar = float(g.abs_r());
+    t = float(g.t);
   }
-  const Folded g = fold(x);  // |x| >= 2^16 (BF16), +-Inf, NaN
-  f.q = g.q;
-  f.hr = g.hr;
-  f.row = g.row;
-  f.ar = float(g.abs_r());
-  return forms(g, tb);
+  const LinF c = tb.f[f.row];
+  const float n = __builtin_fmaf(c.sN, t, c.iN);
+  const float d = __builtin_fmaf(c.sD, t, c.iD);
+  return Forms{n, d, __builtin_fmaf(n, n, d * d)};
 }
 
 // ---------------------------------------------------------------------------
@@ -581,7 +611,7 @@ __device__ inline Folded64 fold64(double x) {
 struct Forms64 {
   double n, d, q;
 };
-__device__ inline Forms64 forms64(const Folded64 &f, const Tables &tb) {
+__device__ inline Forms64 forms64(const Folded64 &f, const TablesFwd &tb) {
   const Lin a = tb.n[f.row], b = tb.d[f.row];
   const double nd = __builtin_fma(a.s, f.t, a.i);
   const double dd = __builtin_fma(b.s, f.t, b.i);
