@@ -27,6 +27,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, AMD published
 METRIC = ("Gelem/s + % HBM peak, ta_sincos FP32 2^28 vs HIP sinf/cosf at "
           "stated max err")
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "ta_sincos_tan_f32_2p28_pmc.txt")
+WARM_S = 0.3  # seconds of untimed load before each secondary measurement
 
 
 def log(msg):
@@ -46,12 +47,21 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def time_launches(fn, steps, warmup, torch):
+def time_launches(fn, steps, warmup, torch, warm_seconds=0.0):
     """Per-launch durations (ms) with HIP events on torch's current stream,
-    which is the stream every ta_* call launches on."""
+    which is the stream every ta_* call launches on.  `warmup` untimed
+    launches first, then, if `warm_seconds` > 0, more until that much wall
+    time has passed: the GPU clock drops while it idles (host-side setup
+    between workloads) and takes a fraction of a second of load to return to
+    its sustained level."""
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
+    t_end = time.perf_counter() + warm_seconds
+    while time.perf_counter() < t_end:
+        for _ in range(10):
+            fn()
+        torch.cuda.synchronize()
     ev = [(torch.cuda.Event(enable_timing=True),
            torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     t0 = time.perf_counter()
@@ -89,7 +99,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=300)
     ap.add_argument("--no-extras", action="store_true",
                     help="only the headline kernel (for profiling runs)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
@@ -272,7 +282,7 @@ def comparators(x, x_host, n, args, torch, ta, np):
         def f(kind=kind):
             ta.ta_builtin_sincos(x, ys, yc, yt, kind=kind)
         log(f"timing {label}")
-        per, total, _ = time_launches(f, args.steps, args.warmup, torch)
+        per, total, _ = time_launches(f, args.steps, args.warmup, torch, WARM_S)
         ms = total / args.steps
         res[label] = {"gelem_s": round(n / (ms * 1e-3) / 1e9, 2),
                       "ms": round(ms, 5),
@@ -282,7 +292,7 @@ def comparators(x, x_host, n, args, torch, ta, np):
     def fp():
         ta.ta_paper_sincos(x, ys, yc, yt, 0)
     log("timing ta_paper_sincos (the paper's literal FISR arithmetic)")
-    per, total, _ = time_launches(fp, args.steps, args.warmup, torch)
+    per, total, _ = time_launches(fp, args.steps, args.warmup, torch, WARM_S)
     ms = total / args.steps
     res["ta_paper_sincos_fisr_fp64"] = {
         "gelem_s": round(n / (ms * 1e-3) / 1e9, 2), "ms": round(ms, 5),
@@ -290,21 +300,21 @@ def comparators(x, x_host, n, args, torch, ta, np):
 
     def f2():
         ta.ta_sincos(x, ys, yc, None)
-    per, total, _ = time_launches(f2, args.steps, args.warmup, torch)
+    per, total, _ = time_launches(f2, args.steps, args.warmup, torch, WARM_S)
     ms = total / args.steps
     res["ta_sincos_2out"] = {"gelem_s": round(n / (ms * 1e-3) / 1e9, 2),
                              "gbs": round(12 * n / (ms * 1e-3) / 1e9, 1)}
 
     def f3():
         ta.ta_taylor_sin(x, ys, 5)
-    per, total, _ = time_launches(f3, args.steps, args.warmup, torch)
+    per, total, _ = time_launches(f3, args.steps, args.warmup, torch, WARM_S)
     ms = total / args.steps
     res["ta_taylor_sin_5"] = {"gelem_s": round(n / (ms * 1e-3) / 1e9, 2),
                               "gbs": round(8 * n / (ms * 1e-3) / 1e9, 1)}
 
     def f4():
         ta.ta_sin(x, ys)
-    per, total, _ = time_launches(f4, args.steps, args.warmup, torch)
+    per, total, _ = time_launches(f4, args.steps, args.warmup, torch, WARM_S)
     ms = total / args.steps
     res["ta_sin"] = {"gelem_s": round(n / (ms * 1e-3) / 1e9, 2),
                      "gbs": round(8 * n / (ms * 1e-3) / 1e9, 1)}
@@ -316,7 +326,7 @@ def comparators(x, x_host, n, args, torch, ta, np):
     def fe():
         ta.ta_sincos_encode(xe, ye, nf)
     log("timing ta_sincos_encode (8 frequencies)")
-    per, total, _ = time_launches(fe, args.steps, args.warmup, torch)
+    per, total, _ = time_launches(fe, args.steps, args.warmup, torch, WARM_S)
     ms = total / args.steps
     res["ta_sincos_encode_8freq"] = {
         "n": ne, "gelem_s": round(ne / (ms * 1e-3) / 1e9, 2),
@@ -326,7 +336,7 @@ def comparators(x, x_host, n, args, torch, ta, np):
 
     def fc():
         ta.ta_copy([x], [ys, yc, yt])
-    per, total, _ = time_launches(fc, args.steps, args.warmup, torch)
+    per, total, _ = time_launches(fc, args.steps, args.warmup, torch, WARM_S)
     ms = total / args.steps
     res["copy_1in_3out_ceiling"] = {"gbs": round(16 * n / (ms * 1e-3) / 1e9, 1),
                                     "ms": round(ms, 5)}
@@ -337,7 +347,7 @@ def comparators(x, x_host, n, args, torch, ta, np):
         ys.fill_(1.0)
         yc.fill_(2.0)
         yt.fill_(3.0)
-    per, total, _ = time_launches(fills, max(5, args.steps // 4), 3, torch)
+    per, total, _ = time_launches(fills, max(5, args.steps // 4), 3, torch, WARM_S)
     ms = total / max(5, args.steps // 4)
     res["torch_fill_3_arrays_write_only"] = {
         "gbs": round(12 * n / (ms * 1e-3) / 1e9, 1)}
@@ -373,7 +383,8 @@ def extras(args, torch, ta, dev):
                               ("torch_sin_then_g_times_cos", torch_ref, 28),
                               ("copy_2in_2out_ceiling", copy22, 16)):
         log(f"timing {label}")
-        per, total, _ = time_launches(fn, max(5, args.steps // 2), 3, torch)
+        per, total, _ = time_launches(fn, max(5, args.steps // 2), 3, torch,
+                                      WARM_S)
         ms = total / max(5, args.steps // 2)
         res[label] = {"ms": round(ms, 5),
                       "gelem_s": round(n / (ms * 1e-3) / 1e9, 2),
@@ -416,7 +427,7 @@ def other_workloads(args, torch, ta, dev):
     gen = torch.Generator(device=dev).manual_seed(2024873)
 
     def timed(fn):
-        per, total, _ = time_launches(fn, steps, 3, torch)
+        per, total, _ = time_launches(fn, steps, 3, torch, WARM_S)
         return total / steps
 
     import numpy as np
