@@ -149,34 +149,50 @@ def test_forward_wide_strided_sweep(dev):
     say(f"wide sweep max ulp {worst}")
 
 
-def test_graph_capture_replays(dev):
-    """The launch is capturable: replay a captured ta_sincos several times,
-    with eager work between replays, and compare every replay bit for bit
-    with the eager result."""
-    x = wl.small_uniform(1 << 16, seed=101)
-    xd = to_dev(x, dev)
-    ys, yc, yt = (torch.empty_like(xd) for _ in range(3))
-    ta.ta_sincos(xd, ys, yc, yt)
-    eager = [host(t).copy() for t in (ys, yc, yt)]
-    say("graph capture")
+@pytest.mark.parametrize("tdt", [torch.float32, torch.bfloat16, torch.float64])
+def test_graph_capture_replays(dev, tdt):
+    """The launch is capturable: replay a captured ta_sincos and a fused
+    forward+backward several times, with eager work between replays, and
+    compare every replay bit for bit with the eager result."""
+    x = wl.small_uniform((1 << 16) + 3, seed=101)
+    xd = torch.from_numpy(x).to(dev).to(tdt)
+    gd = torch.ones_like(xd)
+    outs = [torch.empty_like(xd) for _ in range(5)]
+
+    def launch():
+        ta.ta_sincos(xd, outs[0], outs[1], outs[2])
+        ta.ta_sin_fwdbwd(xd, gd, outs[3], outs[4])
+
+    launch()
+    torch.cuda.synchronize()
+    eager = [t.clone() for t in outs]
+    say(f"graph capture {tdt}")
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
-        ta.ta_sincos(xd, ys, yc, yt)
+        launch()
     for rep in range(4):
-        for t in (ys, yc, yt):
+        for t in outs:
             t.fill_(float(rep + 7))
         torch.cuda.synchronize()
         graph.replay()
         torch.cuda.synchronize()
-        for t, e in zip((ys, yc, yt), eager):
-            assert np.array_equal(host(t).view(np.uint32), e.view(np.uint32))
+        for t, e in zip(outs, eager):
+            assert torch.equal(t, e), (tdt, rep)
 
 
 def test_concurrent_host_threads(dev):
-    """Calls from several host threads on their own streams."""
+    """Calls from several host threads on their own streams, FP32, BF16
+    and FP64 kernels at once; each result equals the same call made alone."""
     import threading
-    xs = [wl.small_uniform(1 << 18, seed=110 + i) for i in range(4)]
-    refs = [oracle.forward(x.astype(np.float64))["sin"] for x in xs]
+    dts = [torch.float32, torch.bfloat16, torch.float64, torch.float32]
+    xs = [torch.from_numpy(wl.small_uniform(1 << 18, seed=110 + i)).to(dev)
+          .to(dts[i]) for i in range(4)]
+    alone = []
+    for xd in xs:
+        y = torch.empty_like(xd)
+        ta.ta_sin(xd, y)
+        alone.append(y)
+    torch.cuda.synchronize()
     outs = [None] * 4
     errors = []
 
@@ -184,12 +200,11 @@ def test_concurrent_host_threads(dev):
         try:
             stream = torch.cuda.Stream()
             with torch.cuda.stream(stream):
-                xd = torch.from_numpy(xs[i]).to(dev, non_blocking=False)
-                y = torch.empty_like(xd)
+                y = torch.empty_like(xs[i])
                 for _ in range(20):
-                    ta.ta_sin(xd, y)
+                    ta.ta_sin(xs[i], y)
                 stream.synchronize()
-                outs[i] = y.cpu().numpy()
+                outs[i] = y
         except Exception as e:  # reported below
             errors.append(e)
 
@@ -200,8 +215,8 @@ def test_concurrent_host_threads(dev):
     for t in threads:
         t.join()
     assert not errors, errors
-    for o, r in zip(outs, refs):
-        assert ulp_error(o, r).max() <= 4.0
+    for o, a in zip(outs, alone):
+        assert torch.equal(o, a)
 
 
 def test_forward_throughput_mix_full_size(dev):
