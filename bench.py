@@ -319,6 +319,26 @@ def comparators(x, x_host, n, args, torch, ta, np):
     res["ta_sin"] = {"gelem_s": round(n / (ms * 1e-3) / 1e9, 2),
                      "gbs": round(8 * n / (ms * 1e-3) / 1e9, 1)}
 
+    # the FP32 fold and forms (TA_FLAG_FORCE_FP32_REDUCTION), fused and sin
+    fl = ta.TA_FLAG_FORCE_FP32_REDUCTION
+
+    def f5():
+        ta.ta_sincos_ex(x, ys, yc, yt, fl)
+    log("timing ta_sincos_ex with the FP32 reduction")
+    per, total, _ = time_launches(f5, args.steps, args.warmup, torch, WARM_S)
+    ms = total / args.steps
+    res["ta_sincos_tan_fp32_reduction"] = {
+        "gelem_s": round(n / (ms * 1e-3) / 1e9, 2),
+        "gbs": round(16 * n / (ms * 1e-3) / 1e9, 1),
+        "error_vs_libm": errors({"sin": ys, "cos": yc, "tan": yt})}
+
+    def f6():
+        ta.ta_sin_ex(x, ys, fl)
+    per, total, _ = time_launches(f6, args.steps, args.warmup, torch, WARM_S)
+    ms = total / args.steps
+    res["ta_sin_fp32_reduction"] = {"gelem_s": round(n / (ms * 1e-3) / 1e9, 2),
+                                    "gbs": round(8 * n / (ms * 1e-3) / 1e9, 1)}
+
     ne, nf = 1 << 24, 8
     xe = x[:ne]
     ye = torch.empty(2 * nf * ne, device=x.device)

@@ -66,11 +66,19 @@ enum {
    * sign is applied, when the folded angle is within 1e-3 of pi/2.  Off by
    * default (the formula is then used all the way to the pole). */
   TA_FLAG_TAN_GUARD = 1u,
-  /* Reduce the argument in FP64.  Accepted by every call that takes flags
-   * and changes nothing: every reduction here is already FP64 (Cody-Waite
-   * below 2^29, a 2/pi bit-table reduction above).  Bit 4u (an FP32
-   * reduction) is not provided and is rejected with TA_EINVAL. */
+  /* Reduce the argument in FP64 (Cody-Waite below 2^29, a 2/pi bit-table
+   * reduction above).  This is the default for FP32 and FP64 storage, so
+   * the flag changes nothing there; it is accepted by every call that takes
+   * flags.  16-bit storage always evaluates in FP32 (below). */
   TA_FLAG_FORCE_FP64_REDUCTION = 2u,
+  /* Forward *_ex calls: reduce and evaluate in FP32, the evaluation 16-bit
+   * storage always uses (three-word FP32 Cody-Waite for |x| < 2^16, the
+   * FP64 fold above; N, D, Q by FP32 FMAs), keeping the refined inverse
+   * square root and reciprocal for FP32 outputs.  FP32 results are then
+   * within 4.5 FP32 ulp of the formula (4.36 measured over every FP32
+   * below 2^16) instead of 3.5.  No effect for 16-bit storage; TA_EINVAL
+   * with TA_F64 or with TA_FLAG_FORCE_FP64_REDUCTION. */
+  TA_FLAG_FORCE_FP32_REDUCTION = 4u,
   /* ta_paper_sincos only: index the pieces by floor(rho / 0.261) as the
    * pseudocode of proposed_sin / proposed_tan does (clamped to the last
    * piece) instead of the pi/12 intervals of Section 2. */
@@ -85,6 +93,13 @@ ta_status ta_sin(const void *x, void *y, int64_t n, ta_dtype dt,
 /* y[i] = cos_a(x[i]).  Section 2, cosine cases. */
 ta_status ta_cos(const void *x, void *y, int64_t n, ta_dtype dt,
                  hipStream_t stream);
+/* The same with flag bits (TA_FLAG_FORCE_FP64_REDUCTION,
+ * TA_FLAG_FORCE_FP32_REDUCTION; TA_FLAG_TAN_GUARD is accepted and affects
+ * tan outputs only). */
+ta_status ta_sin_ex(const void *x, void *y, int64_t n, ta_dtype dt,
+                    uint32_t flags, hipStream_t stream);
+ta_status ta_cos_ex(const void *x, void *y, int64_t n, ta_dtype dt,
+                    uint32_t flags, hipStream_t stream);
 /* y[i] = tan_a(x[i]).  Section 2, tangent cases; finite up to the
  * pole (the last piece's D vanishes only at exactly pi/2). */
 ta_status ta_tan(const void *x, void *y, int64_t n, ta_dtype dt,
@@ -94,7 +109,7 @@ ta_status ta_tan(const void *x, void *y, int64_t n, ta_dtype dt,
 ta_status ta_sincos(const void *x, void *ys, void *yc, void *yt, int64_t n,
                     ta_dtype dt, hipStream_t stream);
 /* Same as above with flag bits (TA_FLAG_TAN_GUARD affects tan outputs;
- * TA_FLAG_FORCE_FP64_REDUCTION is accepted). */
+ * TA_FLAG_FORCE_FP64_REDUCTION, TA_FLAG_FORCE_FP32_REDUCTION). */
 ta_status ta_tan_ex(const void *x, void *y, int64_t n, ta_dtype dt,
                     uint32_t flags, hipStream_t stream);
 ta_status ta_sincos_ex(const void *x, void *ys, void *yc, void *yt, int64_t n,

@@ -31,7 +31,8 @@ __all__ = [
     "sin", "cos", "tan", "sincos", "taylor",
     "SinFn", "CosFn", "TanFn", "SinCosFn",
     "TA_FLAG_TAN_GUARD", "TA_FLAG_LITERAL_DIVISOR",
-    "TA_FLAG_FORCE_FP64_REDUCTION", "paper_sincos", "encode",
+    "TA_FLAG_FORCE_FP64_REDUCTION", "TA_FLAG_FORCE_FP32_REDUCTION",
+    "ta_sin_ex", "ta_cos_ex", "paper_sincos", "encode",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -40,6 +41,7 @@ _LIB = os.path.join(_HERE, "libta.so")
 TA_F32, TA_F16, TA_BF16, TA_F64 = 0, 1, 2, 3
 TA_FLAG_TAN_GUARD = 1
 TA_FLAG_FORCE_FP64_REDUCTION = 2
+TA_FLAG_FORCE_FP32_REDUCTION = 4
 TA_FLAG_LITERAL_DIVISOR = 8
 _DTYPE_CODE = {torch.float32: TA_F32, torch.float16: TA_F16,
                torch.bfloat16: TA_BF16, torch.float64: TA_F64}
@@ -72,6 +74,8 @@ def load(path: str | None = None):
         "ta_cos": [vp, vp, i64, i32, vp],
         "ta_tan": [vp, vp, i64, i32, vp],
         "ta_tan_ex": [vp, vp, i64, i32, u32, vp],
+        "ta_sin_ex": [vp, vp, i64, i32, u32, vp],
+        "ta_cos_ex": [vp, vp, i64, i32, u32, vp],
         "ta_sincos": [vp, vp, vp, vp, i64, i32, vp],
         "ta_sincos_ex": [vp, vp, vp, vp, i64, i32, u32, vp],
         "ta_taylor_sin": [vp, vp, i64, i32, i32, vp],
@@ -172,6 +176,18 @@ def ta_tan(x, y):
     _dev(x, "x"); _same(x, ("y", y))
     n, dt, s = _args(x)
     _check(load().ta_tan(_ptr(x), _ptr(y), n, dt, s))
+
+
+def ta_sin_ex(x, y, flags: int):
+    _dev(x, "x"); _same(x, ("y", y))
+    n, dt, s = _args(x)
+    _check(load().ta_sin_ex(_ptr(x), _ptr(y), n, dt, int(flags), s))
+
+
+def ta_cos_ex(x, y, flags: int):
+    _dev(x, "x"); _same(x, ("y", y))
+    n, dt, s = _args(x)
+    _check(load().ta_cos_ex(_ptr(x), _ptr(y), n, dt, int(flags), s))
 
 
 def ta_tan_ex(x, y, flags: int):

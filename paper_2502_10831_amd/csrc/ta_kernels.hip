@@ -131,21 +131,24 @@ enum : int { kSin = 1, kCos = 2, kTan = 4 };
 
 // LOW: the variant for 16-bit storage.  Its outputs keep 8 (BF16) or 11
 // (FP16) significant bits, so the whole evaluation runs in FP32
-// (fold_forms16) and the hardware inverse square root and reciprocal (each
+// (fold_forms_f32) and the hardware inverse square root and reciprocal (each
 // within about one FP32 ulp) are used without the Newton refinement.
 // Every op names the instance the 16-bit formats launch (Low).
-template <int MASK, bool GUARD, bool LOW = false>
+// F32RED (forward, FP32 storage, TA_FLAG_FORCE_FP32_REDUCTION): the FP32
+// evaluation with the refined inverse square root and reciprocal.
+template <int MASK, bool GUARD, bool LOW = false, bool F32RED = false>
 struct FwdOp {
   static constexpr int NIN = 1;
   static constexpr int NOUT = ((MASK & kSin) ? 1 : 0) + ((MASK & kCos) ? 1 : 0) +
                               ((MASK & kTan) ? 1 : 0);
-  using Table = typename std::conditional<LOW, Tables16, TablesFwd>::type;
+  static constexpr bool kFp32Fold = LOW || F32RED;
+  using Table = typename std::conditional<kFp32Fold, Tables16, TablesFwd>::type;
   using Low = FwdOp<MASK, GUARD, true>;
   __device__ static void apply(const float *in, float *out, const Table &tb,
                                   uint32_t) {
-    if constexpr (LOW) {
+    if constexpr (kFp32Fold) {
       FoldedL f;
-      const Forms v = fold_forms16(in[0], tb, f);
+      const Forms v = fold_forms_f32(in[0], tb, f);
       finish(f, v, out);
     } else {
       const Folded f = fold(in[0]);
@@ -172,6 +175,7 @@ struct FwdOp {
   }
   __device__ static void apply(const double *in, double *out, const Table &tb,
                                uint32_t) {
+    static_assert(!kFp32Fold, "FP64 storage uses the FP64 table");
     const Folded64 f = fold64(in[0]);
     const Forms64 v = forms64(f, tb);
     int o = 0;
@@ -234,7 +238,7 @@ struct BwdOp {
                                   uint32_t) {
     if constexpr (LOW) {
       FoldedL f;
-      const Forms v = fold_forms16(in[0], tb, f);
+      const Forms v = fold_forms_f32(in[0], tb, f);
       finish(f, v, in, out, tb);
     } else {
       const Folded f = fold(in[0]);
@@ -305,7 +309,7 @@ struct SinCosBwdOp {
                                   uint32_t) {
     if constexpr (LOW) {
       FoldedL f;
-      const Forms v = fold_forms16(in[0], tb, f);
+      const Forms v = fold_forms_f32(in[0], tb, f);
       finish(f, v, in, out, tb);
     } else {
       const Folded f = fold(in[0]);
@@ -850,6 +854,35 @@ ta_status fwd(const void *x, void *const *outs, int64_t n, ta_dtype dt,
   return run<FwdOp<MASK, GUARD>>(in, outs, n, dt, s);
 }
 
+// Flags of the *_ex forward calls.  TA_FLAG_FORCE_FP32_REDUCTION selects the
+// FP32 evaluation for FP32 storage (16-bit storage always uses it); it is
+// not valid for FP64 storage or together with TA_FLAG_FORCE_FP64_REDUCTION.
+inline ta_status check_fwd_flags(uint32_t flags, ta_dtype dt) {
+  if (!dtype_ok(dt)) return TA_EDTYPE;
+  const uint32_t known = TA_FLAG_TAN_GUARD | TA_FLAG_FORCE_FP64_REDUCTION |
+                         TA_FLAG_FORCE_FP32_REDUCTION;
+  if (flags & ~known) return TA_EINVAL;
+  if ((flags & TA_FLAG_FORCE_FP32_REDUCTION) &&
+      ((flags & TA_FLAG_FORCE_FP64_REDUCTION) || dt == TA_F64))
+    return TA_EINVAL;
+  return TA_OK;
+}
+
+template <int MASK, bool GUARD>
+ta_status fwd_ex(const void *x, void *const *outs, int64_t n, ta_dtype dt,
+                 uint32_t flags, hipStream_t s) {
+  const ta_status st = check_fwd_flags(flags, dt);
+  if (st != TA_OK) return st;
+  if ((flags & TA_FLAG_FORCE_FP32_REDUCTION) && dt == TA_F32) {
+    using Op = FwdOp<MASK, GUARD, false, true>;
+    const void *in[1] = {x};
+    const ta_status c = check_common(in, Op::NIN, outs, Op::NOUT, n, dt);
+    if (c != TA_OK || n == 0) return c;
+    return finish(launch_map<F32, Op>(in, outs, n, s, 0u));
+  }
+  return fwd<MASK, GUARD>(x, outs, n, dt, s);
+}
+
 template <int MASK>
 ta_status taylor(const void *x, void *y, int64_t n, int terms, ta_dtype dt,
                  hipStream_t s) {
@@ -886,23 +919,31 @@ using namespace ta;
 // ---------------------------------------------------------------------------
 extern "C" {
 
-ta_status ta_sin(const void *x, void *y, int64_t n, ta_dtype dt, hipStream_t s) {
+ta_status ta_sin_ex(const void *x, void *y, int64_t n, ta_dtype dt,
+                    uint32_t flags, hipStream_t s) {
   void *o[1] = {y};
-  return fwd<kSin, false>(x, o, n, dt, s);
+  return fwd_ex<kSin, false>(x, o, n, dt, flags, s);
+}
+
+ta_status ta_sin(const void *x, void *y, int64_t n, ta_dtype dt, hipStream_t s) {
+  return ta_sin_ex(x, y, n, dt, 0u, s);
+}
+
+ta_status ta_cos_ex(const void *x, void *y, int64_t n, ta_dtype dt,
+                    uint32_t flags, hipStream_t s) {
+  void *o[1] = {y};
+  return fwd_ex<kCos, false>(x, o, n, dt, flags, s);
 }
 
 ta_status ta_cos(const void *x, void *y, int64_t n, ta_dtype dt, hipStream_t s) {
-  void *o[1] = {y};
-  return fwd<kCos, false>(x, o, n, dt, s);
+  return ta_cos_ex(x, y, n, dt, 0u, s);
 }
 
 ta_status ta_tan_ex(const void *x, void *y, int64_t n, ta_dtype dt,
                     uint32_t flags, hipStream_t s) {
-  if (flags & ~uint32_t(TA_FLAG_TAN_GUARD | TA_FLAG_FORCE_FP64_REDUCTION))
-    return TA_EINVAL;
   void *o[1] = {y};
-  if (flags & TA_FLAG_TAN_GUARD) return fwd<kTan, true>(x, o, n, dt, s);
-  return fwd<kTan, false>(x, o, n, dt, s);
+  if (flags & TA_FLAG_TAN_GUARD) return fwd_ex<kTan, true>(x, o, n, dt, flags, s);
+  return fwd_ex<kTan, false>(x, o, n, dt, flags, s);
 }
 
 ta_status ta_tan(const void *x, void *y, int64_t n, ta_dtype dt, hipStream_t s) {
@@ -911,16 +952,14 @@ ta_status ta_tan(const void *x, void *y, int64_t n, ta_dtype dt, hipStream_t s) 
 
 ta_status ta_sincos_ex(const void *x, void *ys, void *yc, void *yt, int64_t n,
                        ta_dtype dt, uint32_t flags, hipStream_t s) {
-  if (flags & ~uint32_t(TA_FLAG_TAN_GUARD | TA_FLAG_FORCE_FP64_REDUCTION))
-    return TA_EINVAL;
   if (yt) {
     void *o[3] = {ys, yc, yt};
     if (flags & TA_FLAG_TAN_GUARD)
-      return fwd<kSin | kCos | kTan, true>(x, o, n, dt, s);
-    return fwd<kSin | kCos | kTan, false>(x, o, n, dt, s);
+      return fwd_ex<kSin | kCos | kTan, true>(x, o, n, dt, flags, s);
+    return fwd_ex<kSin | kCos | kTan, false>(x, o, n, dt, flags, s);
   }
   void *o[2] = {ys, yc};
-  return fwd<kSin | kCos, false>(x, o, n, dt, s);
+  return fwd_ex<kSin | kCos, false>(x, o, n, dt, flags, s);
 }
 
 ta_status ta_sincos(const void *x, void *ys, void *yc, void *yt, int64_t n,

@@ -293,22 +293,27 @@ __device__ inline Forms forms(const Folded &f, const TablesFwd &tb) {
 }
 
 // ---------------------------------------------------------------------------
-// 16-bit storage: the whole evaluation in FP32 (outputs keep 8 or 11 bits).
-// For |x| < 2^16 (every FP16 value, BF16 below 65536): q = rint(x RN(2/pi))
-// and a three-word Cody-Waite r = x - q pi/2 (the first step exact: x and
-// q C1 are multiples of 2^-23 there and |r| < 1), relative error ~2^-23.
-// The rounded product can put q on the neighbour of the nearest quadrant
-// near odd multiples of pi/4, leaving |r| up to ~0.8: slot 3 of the table
-// continues both families, so that costs nothing.  Larger BF16 values take
-// the FP64 fold.  Then t = |r| 180/pi, N, D, Q by FP32 FMAs from the FP32
-// table row.
+// The evaluation in FP32: always for 16-bit storage (outputs keep 8 or 11
+// bits), and for FP32 storage with TA_FLAG_FORCE_FP32_REDUCTION.
+// For |x| < 2^16 (every FP16 value, BF16 below 65536): q = the integer
+// nearest x RN(2/pi), by one FMA adding 1.5 2^23 (q is then the low bits of
+// that sum, and the sum less 1.5 2^23 is +0 when q = 0), and a three-word
+// Cody-Waite r = x - q pi/2 (the first step exact: x and q C1 are multiples
+// of 2^-23 there and |r| < 1), relative error ~2^-23.  The three words are
+// rounded down, so all are positive and each -q Ci is -0 when q = 0: r then
+// keeps the sign of a zero x.  The rounding of 2/pi can put q on the neighbour
+// of the nearest quadrant near odd multiples of pi/4, leaving |r| a little
+// above pi/4: slot 3 of the table continues both families, so that costs
+// nothing.  Larger BF16 values take the FP64 fold.  Then t = |r| 180/pi, N, D, Q by FP32 FMAs from the FP32
+// table row.  Relative errors (u = 2^-24): r 2u, t 4u, N and D 5u.
 // ---------------------------------------------------------------------------
 constexpr float kTwoOverPiF = 0x1.45f306p-1f;  // RN24(2/pi)
-constexpr float kPio2F1 = 0x1.921fb6p+0f;      // RN24(pi/2)
-constexpr float kPio2F2 = -0x1.777a5cp-25f;    // RN24(pi/2 - F1)
-constexpr float kPio2F3 = -0x1.ee59dap-50f;    // RN24(pi/2 - F1 - F2)
+constexpr float kPio2F1 = 0x1.921fb4p+0f;      // RD24(pi/2)
+constexpr float kPio2F2 = 0x1.4442d0p-24f;     // RD24(pi/2 - F1)
+constexpr float kPio2F3 = 0x1.84698ap-48f;     // RN24(pi/2 - F1 - F2)
 constexpr float kDegPerRadF = 0x1.ca5dc2p+5f;  // RN24(180/pi)
 constexpr float kSmall16 = 0x1p16f;
+constexpr float kRoundMagicF = 0x1.8p23f;      // 1.5 * 2^23
 
 struct FoldedL {
   uint32_t q;    // quadrant, low bits
@@ -318,14 +323,15 @@ struct FoldedL {
   __device__ float abs_r() const { return ar; }
 };
 
-__device__ inline Forms fold_forms16(float x, const Tables16 &tb, FoldedL &f) {
+__device__ inline Forms fold_forms_f32(float x, const Tables16 &tb, FoldedL &f) {
   float t;
   if (__builtin_expect(__builtin_fabsf(x) < kSmall16, 1)) {
-    const float qf = __builtin_rintf(x * kTwoOverPiF);
+    const float qb = __builtin_fmaf(x, kTwoOverPiF, kRoundMagicF);
+    const float qf = qb - kRoundMagicF;
     float r = __builtin_fmaf(-qf, kPio2F1, x);
     r = __builtin_fmaf(-qf, kPio2F2, r);
     r = __builtin_fmaf(-qf, kPio2F3, r);
-    f.q = uint32_t(int32_t(qf));
+    f.q = __float_as_uint(qb);  // 2^22 + q in the mantissa: low bits of q
     f.hr = __float_as_uint(r);
     f.ar = __builtin_fabsf(r);
     t = f.ar * kDegPerRadF;

@@ -118,6 +118,8 @@ def check_16(name, kind, gpu_raw, ref, tol_abs, alt=None, near=None):
             return (g >= lo) & (g <= hi)
 
     ok = ok_for(ref) | nan_ref
+    zero = ref == 0
+    ok[zero] &= np.signbit(g[zero]) == np.signbit(ref[zero])
     if alt is not None and near is not None and near.any():
         fn = name.rsplit("-", 1)[-1].rsplit(":", 1)[-1]
         ok_alt = ok_for(np.where(near, alt[fn], ref))

@@ -61,17 +61,26 @@ def test_unary_validation(lib):
 def test_sincos_validation(lib):
     f = _fn(lib, "ta_sincos_ex", vp, vp, vp, vp, i64, i32, u32, vp)
     assert f(A, B, None, None, 16, F32, 0, None) == EINVAL    # yc required
-    assert f(A, B, B + 32, None, 16, F32, 4, None) == EINVAL  # FP32 reduction
+    # FP32 reduction: not for FP64 storage, not with the FP64 flag
+    assert f(A, B, B + 128, None, 16, F64, 4, None) == EINVAL
+    assert f(A, B, B + 32, None, 16, F32, 6, None) == EINVAL
     assert f(A, B, B + 32, None, 16, F32, 8, None) == EINVAL  # paper-only flag
+    assert f(A, B, B + 32, None, 16, F32, 16, None) == EINVAL  # unknown
     assert f(A, B, B + 32, B + 16, 16, F32, 0, None) == EOVERLAP
     assert f(A, B, B, None, 16, F32, 0, None) == EOVERLAP     # ys == yc
     assert f(A, B, B + 64, B + 128, 16, 4, 0, None) == EDTYPE
     # FP64 elements are 8 bytes: 16 of them end at +128
     assert f(A, B, B + 64, None, 16, F64, 0, None) == EOVERLAP
     assert f(A, B, B + 64, None, 0, F32, 0, None) == OK
-    g = _fn(lib, "ta_tan_ex", vp, vp, i64, i32, u32, vp)
-    assert g(A, B, 16, F32, 4, None) == EINVAL
-    assert g(A, B, 16, F32, 16, None) == EINVAL
+    for name in ("ta_sin_ex", "ta_cos_ex", "ta_tan_ex"):
+        g = _fn(lib, name, vp, vp, i64, i32, u32, vp)
+        assert g(A, B, 16, F64, 4, None) == EINVAL, name
+        assert g(A, B, 16, F32, 6, None) == EINVAL, name
+        assert g(A, B, 16, F32, 8, None) == EINVAL, name
+        assert g(A, B, 16, F32, 16, None) == EINVAL, name
+        assert g(A, B, 16, 7, 0, None) == EDTYPE, name
+        assert g(A, A + 4, 16, F32, 4, None) == EOVERLAP, name
+        assert g(None, None, 0, F32, 4, None) == OK, name
 
 
 def test_taylor_validation(lib):

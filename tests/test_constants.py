@@ -44,6 +44,42 @@ def test_reduction_constants(text):
     assert _const(text, "kLargeArg64") == 2.0 ** 29
 
 
+def _const_f(text, name):
+    m = re.search(rf"constexpr float {name} = ([0-9a-fx.p+-]+)f;", text)
+    assert m, name
+    return mpmath.mpf(float.fromhex(m.group(1)))
+
+
+def _round24(v, down=False):
+    """v > 0 to 24 significant bits: to nearest (ties to even), or down."""
+    e = int(mpmath.floor(mpmath.log(v, 2)))
+    scaled = v * mpmath.mpf(2) ** (23 - e)
+    m = mpmath.floor(scaled) if down else mpmath.nint(scaled)
+    return m * mpmath.mpf(2) ** (e - 23)
+
+
+def test_fp32_reduction_constants(text):
+    """The FP32 evaluation (16-bit storage, and FP32 storage under the FP32
+    reduction flag): RN24(2/pi), pi/2 as three words rounded down (all
+    positive, so -q Ci is -0 for q = 0 and a zero x keeps its sign; the first
+    a multiple of 2^-23, so x - q C1 is exact below 2^16), RN24(180/pi)."""
+    mpmath.mp.prec = 400
+    pi = mpmath.pi
+    assert _const_f(text, "kTwoOverPiF") == _round24(2 / pi)
+    f1 = _const_f(text, "kPio2F1")
+    f2 = _const_f(text, "kPio2F2")
+    f3 = _const_f(text, "kPio2F3")
+    assert f1 == _round24(pi / 2, down=True)
+    assert f2 == _round24(pi / 2 - f1, down=True)
+    assert f3 == _round24(pi / 2 - f1 - f2)
+    assert f1 > 0 and f2 > 0 and f3 > 0
+    assert (f1 * 2 ** 23) == mpmath.floor(f1 * 2 ** 23)
+    assert abs(pi / 2 - f1 - f2 - f3) < mpmath.mpf(2) ** -72
+    assert _const_f(text, "kDegPerRadF") == _round24(180 / pi)
+    assert _const_f(text, "kRoundMagicF") == 1.5 * 2 ** 23
+    assert _const_f(text, "kSmall16") == 2 ** 16
+
+
 def test_two_over_pi_bits(text):
     mpmath.mp.prec = 400
     m = re.search(r"kTwoOverPiBits\[8\] = \{([^}]*)\}", text)

@@ -709,6 +709,64 @@ def test_comparators_and_copy(dev):
         assert torch.equal(o, xd)
 
 
+def test_force_fp32_reduction_flag(dev):
+    """TA_FLAG_FORCE_FP32_REDUCTION on FP32 storage: the FP32 fold and forms
+    (the 16-bit evaluation) with refined normalisation, within 4.5 ulp of the
+    formula on a strided sweep of every binade below 2^16, large arguments
+    (the FP64 fold above 2^16) and the FP32 values closest to multiples of
+    pi/2.  On 16-bit storage the flag changes no bit; flags 0 give the bits
+    of the plain calls."""
+    flag = ta.TA_FLAG_FORCE_FP32_REDUCTION
+    pos = np.arange(0, 0x47800000, 251, dtype=np.uint32).view(np.float32)
+    rng = np.random.default_rng(5)
+    parts = [pos, -pos, wl.log_magnitude(1 << 20, seed=6),
+             _closest_to_multiples_of_half_pi(),
+             rng.uniform(-1e30, 1e30, 4096).astype(np.float32)]
+    x = np.concatenate(parts).astype(np.float32)
+    say(f"force fp32 reduction n={x.size}")
+    xd = to_dev(x, dev)
+    out = {}
+    for name, fn in (("sin", ta.ta_sin_ex), ("cos", ta.ta_cos_ex),
+                     ("tan", ta.ta_tan_ex)):
+        y = torch.empty_like(xd)
+        fn(xd, y, flag)
+        out[name] = host(y)
+    ys, yc, yt = (torch.empty_like(xd) for _ in range(3))
+    ta.ta_sincos_ex(xd, ys, yc, yt, flag)
+    out["f3_sin"], out["f3_cos"], out["f3_tan"] = host(ys), host(yc), host(yt)
+    ref = oracle.forward(x.astype(np.float64))
+    near, alt = neighbour_values(x.astype(np.float64))
+    worst = {}
+    for key, got in out.items():
+        fn = key.split("_")[-1]
+        worst[key] = check_f32(f"fp32red:{key}", x, got, ref[fn], alt, near,
+                               max_ulp=4.5)
+    for k in ("sin", "cos", "tan"):
+        assert np.array_equal(out[k].view(np.uint32),
+                              out["f3_" + k].view(np.uint32))
+    say(f"force fp32 reduction: max ulp {worst}")
+    # flags 0 on the _ex calls give the plain calls' bits
+    xs = xd[: 1 << 16]
+    for plain, ex in ((ta.ta_sin, ta.ta_sin_ex), (ta.ta_cos, ta.ta_cos_ex),
+                      (ta.ta_tan, ta.ta_tan_ex)):
+        a, b = torch.empty_like(xs), torch.empty_like(xs)
+        plain(xs, a)
+        ex(xs, b, 0)
+        torch.cuda.synchronize()
+        assert torch.equal(a.view(torch.int32), b.view(torch.int32))
+    # 16-bit storage already evaluates this way
+    for tdt in (torch.bfloat16, torch.float16):
+        h = torch.from_numpy(wl.throughput_mix(1 << 16, seed=78)).to(dev)
+        h = h.clamp(-6e4, 6e4).to(tdt)
+        a = [torch.empty_like(h) for _ in range(3)]
+        b = [torch.empty_like(h) for _ in range(3)]
+        ta.ta_sincos_ex(h, *a, 0)
+        ta.ta_sincos_ex(h, *b, flag)
+        torch.cuda.synchronize()
+        for u, v in zip(a, b):
+            assert torch.equal(u.view(torch.int16), v.view(torch.int16))
+
+
 def test_force_fp64_reduction_flag_changes_nothing(dev):
     """The flag is accepted and every reduction is FP64 already: identical
     bits with and without it, FP32 and FP64 storage, forward and paper."""
