@@ -469,7 +469,16 @@ def test_taylor(dev, terms):
 # backward and fused forward+backward
 # ---------------------------------------------------------------------------
 
-GRAD_ULPS = 12  # derivation: omega (4 roundings) x output (2.5 ulp) x g
+# FP32 storage: omega (4 roundings), the output (2.5 ulp) and g; a host build
+# of the arithmetic over every FP32 in [2^-31, 2^16) and a 1/101 sample
+# above peaks at 7.5 u (relative) before the product with g.
+GRAD_ULPS = 12
+# 16-bit storage: the unrefined inverse square root and reciprocal (each
+# within an FP32 ulp) enter omega = kdet y^2 twice and the output once; a
+# host build of the arithmetic over every FP16 and BF16 input, with the
+# estimates pushed an ulp either way, peaks at 12.6 u (relative) before the
+# product with g (0.5 u more) and the rounding to 16 bits.
+GRAD_ULPS_16 = 14
 
 
 def _grad_case(n, sigma, seed):
@@ -539,7 +548,7 @@ def test_backward_16bit(dev, kind):
         bwd(xd, gd, gx)
         raw = host(gx.view(torch.int16)).view(np.uint16)
         ref = g64 * rg[name]
-        tol = GRAD_ULPS * U24 * np.abs(ref) + ulp32(ref)
+        tol = GRAD_ULPS_16 * U24 * np.abs(ref) + ulp32(ref)
         bad_free = ~near
         check_16(f"bwd-{name}", kind, raw[bad_free], ref[bad_free],
                  tol[bad_free])
@@ -639,6 +648,57 @@ def test_fused_fwdbwd_full_size(dev):
     _check_grad("fwdbwd-gx", xs, gs, gxs, rg["sin"],
                 np.abs(gs.astype(np.float64) * rg["sin"]))
     del x, g, y, gx
+
+
+@pytest.mark.parametrize("kind", ["f32", "bf16"])
+def test_activation_every_element(dev, kind):
+    """[64, 4096, 256] activation, x ~ N(0, 3^2), g ~ N(0, 1) (BF16: both
+    rounded to nearest even): forward, backward and the fused kernel on the
+    whole tensor, every element checked against the oracle in 2^24-element
+    chunks; the fused kernel's outputs equal the separate calls' bits."""
+    tdt = torch.float32 if kind == "f32" else torch.bfloat16
+    n = 64 * 4096 * 256
+    say(f"activation {kind} n={n}: generating")
+    gen = torch.Generator(device=dev).manual_seed(wl.SEED)
+    x = (torch.randn(n, device=dev, generator=gen) * 3.0).to(tdt)
+    g = torch.randn(n, device=dev, generator=gen).to(tdt)
+    y1, gx1 = torch.empty_like(x), torch.empty_like(x)
+    y2, gx2 = torch.empty_like(x), torch.empty_like(x)
+    ta.ta_sin(x, y1)
+    ta.ta_sin_bwd(x, g, gx1)
+    ta.ta_sin_fwdbwd(x, g, y2, gx2)
+    torch.cuda.synchronize()
+    iv = torch.int32 if kind == "f32" else torch.int16
+    assert torch.equal(y1.view(iv), y2.view(iv))
+    assert torch.equal(gx1.view(iv), gx2.view(iv))
+    chunk = 1 << 24
+    for lo in range(0, n, chunk):
+        sl = slice(lo, lo + chunk)
+        xs = x[sl].double().cpu().numpy()
+        gs = g[sl].double().cpu().numpy()
+        ref_f = oracle.forward(xs, want=("sin",))["sin"]
+        ref_g = gs * oracle.grad(xs)["sin"]
+        near, alt = neighbour_values(xs)
+        tol = GRAD_ULPS * U24 * np.abs(ref_g) + ulp32(ref_g)
+        if kind == "f32":
+            check_f32("act-y:sin", xs, host(y2[sl]), ref_f, alt, near)
+            gxs = host(gx2[sl]).astype(np.float64)
+        else:
+            raw = host(y2[sl].view(torch.int16)).view(np.uint16)
+            check_16("act-y:sin", "bf16", raw, ref_f, 4 * ulp32(ref_f), alt,
+                     near)
+            # the 16-bit gradient: RNE16 of a value within tol of the oracle
+            tol = GRAD_ULPS_16 * U24 * np.abs(ref_g) + ulp32(ref_g)
+            graw = host(gx2[sl].view(torch.int16)).view(np.uint16)
+            keep = ~near
+            check_16("act-gx:sin", "bf16", graw[keep], ref_g[keep], tol[keep])
+            say(f"activation {kind}: elements {lo}..{lo + chunk} ok")
+            continue
+        bad = (np.abs(gxs - ref_g) > tol) & ~near
+        assert not bad.any(), (kind, lo, xs[bad][:3], gxs[bad][:3],
+                               ref_g[bad][:3])
+        say(f"activation {kind}: elements {lo}..{lo + chunk} ok")
+    del x, g, y1, y2, gx1, gx2
 
 
 # ---------------------------------------------------------------------------
