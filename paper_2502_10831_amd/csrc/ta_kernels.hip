@@ -133,10 +133,13 @@ enum : int { kSin = 1, kCos = 2, kTan = 4 };
 // (FP16) significant bits, so the whole evaluation runs in FP32
 // (fold_forms_f32) and the hardware inverse square root and reciprocal (each
 // within about one FP32 ulp) are used without the Newton refinement.
-// Every op names the instance the 16-bit formats launch (Low).
+// Every op names the instances the 16-bit formats launch: Low for BF16,
+// LowH for FP16, whose finite values all lie below 2^16 (SMALL: no test for
+// the FP64 fold; +-Inf and NaN come out NaN through the FP32 fold too).
 // F32RED (forward, FP32 storage, TA_FLAG_FORCE_FP32_REDUCTION): the FP32
 // evaluation with the refined inverse square root and reciprocal.
-template <int MASK, bool GUARD, bool LOW = false, bool F32RED = false>
+template <int MASK, bool GUARD, bool LOW = false, bool F32RED = false,
+          bool SMALL = false>
 struct FwdOp {
   static constexpr int NIN = 1;
   static constexpr int NOUT = ((MASK & kSin) ? 1 : 0) + ((MASK & kCos) ? 1 : 0) +
@@ -144,11 +147,12 @@ struct FwdOp {
   static constexpr bool kFp32Fold = LOW || F32RED;
   using Table = typename std::conditional<kFp32Fold, Tables16, TablesFwd>::type;
   using Low = FwdOp<MASK, GUARD, true>;
+  using LowH = FwdOp<MASK, GUARD, true, false, true>;
   __device__ static void apply(const float *in, float *out, const Table &tb,
                                   uint32_t) {
     if constexpr (kFp32Fold) {
       FoldedL f;
-      const Forms v = fold_forms_f32(in[0], tb, f);
+      const Forms v = fold_forms_f32<!SMALL>(in[0], tb, f);
       finish(f, v, out);
     } else {
       const Folded f = fold(in[0]);
@@ -200,6 +204,7 @@ struct TaylorOp {
   static constexpr int NOUT = 1;
   using Table = NoTable;
   using Low = TaylorOp;
+  using LowH = TaylorOp;
   __device__ static void apply(const float *in, float *out, const Table &,
                                   uint32_t) {
     const Folded f = fold(in[0]);
@@ -228,17 +233,18 @@ struct TaylorOp {
 //   sin: gx = gy * omega * cos_a     cos: gx = -gy * omega * sin_a
 //   tan: gx = gy * (180/pi) det / D^2
 // WITH_Y also writes the forward value (the fused forward+backward).
-template <int WHICH, bool WITH_Y, bool LOW = false>
+template <int WHICH, bool WITH_Y, bool LOW = false, bool SMALL = false>
 struct BwdOp {
   static constexpr int NIN = 2;  // x, gy
   static constexpr int NOUT = WITH_Y ? 2 : 1;
   using Table = typename std::conditional<LOW, Tables16, TablesBwd>::type;
   using Low = BwdOp<WHICH, WITH_Y, true>;
+  using LowH = BwdOp<WHICH, WITH_Y, true, true>;
   __device__ static void apply(const float *in, float *out, const Table &tb,
                                   uint32_t) {
     if constexpr (LOW) {
       FoldedL f;
-      const Forms v = fold_forms_f32(in[0], tb, f);
+      const Forms v = fold_forms_f32<!SMALL>(in[0], tb, f);
       finish(f, v, in, out, tb);
     } else {
       const Folded f = fold(in[0]);
@@ -299,17 +305,18 @@ struct BwdOp {
 };
 
 // gx = gs * d sin_a/dx + gc * d cos_a/dx = omega (gs cos_a - gc sin_a).
-template <bool HAS_GS, bool HAS_GC, bool LOW = false>
+template <bool HAS_GS, bool HAS_GC, bool LOW = false, bool SMALL = false>
 struct SinCosBwdOp {
   static constexpr int NIN = 1 + (HAS_GS ? 1 : 0) + (HAS_GC ? 1 : 0);
   static constexpr int NOUT = 1;
   using Table = typename std::conditional<LOW, Tables16, TablesBwd>::type;
   using Low = SinCosBwdOp<HAS_GS, HAS_GC, true>;
+  using LowH = SinCosBwdOp<HAS_GS, HAS_GC, true, true>;
   __device__ static void apply(const float *in, float *out, const Table &tb,
                                   uint32_t) {
     if constexpr (LOW) {
       FoldedL f;
-      const Forms v = fold_forms_f32(in[0], tb, f);
+      const Forms v = fold_forms_f32<!SMALL>(in[0], tb, f);
       finish(f, v, in, out, tb);
     } else {
       const Folded f = fold(in[0]);
@@ -352,6 +359,7 @@ struct PaperOp {
                               ((MASK & kTan) ? 1 : 0);
   using Table = PaperTables;
   using Low = PaperOp;
+  using LowH = PaperOp;
   __device__ static void apply(const float *in, float *out, const Table &tb,
                                uint32_t flags) {
     const Folded f = fold(in[0]);
@@ -399,6 +407,7 @@ struct BuiltinOp {
   static constexpr int NOUT = WITH_TAN ? 3 : 2;
   using Table = NoTable;
   using Low = BuiltinOp;
+  using LowH = BuiltinOp;
   __device__ static void apply(const float *in, float *out, const Table &,
                                   uint32_t) {
     const float x = in[0];
@@ -442,6 +451,7 @@ struct CopyOp {
   static constexpr int NOUT = NO;
   using Table = NoTable;
   using Low = CopyOp;
+  using LowH = CopyOp;
   template <class V>
   __device__ static void apply(const V *in, V *out, const Table &, uint32_t) {
 #pragma unroll
@@ -774,7 +784,7 @@ hipError_t launch_dtype(ta_dtype dt, const void *const *in, void *const *out,
                         int64_t n, hipStream_t s, uint32_t flags) {
   switch (dt) {
     case TA_F32: return launch_map<F32, Op>(in, out, n, s, flags);
-    case TA_F16: return launch_map<F16, typename Op::Low>(in, out, n, s, flags);
+    case TA_F16: return launch_map<F16, typename Op::LowH>(in, out, n, s, flags);
     case TA_BF16: return launch_map<BF16, typename Op::Low>(in, out, n, s, flags);
     case TA_F64: return launch_map<F64, Op>(in, out, n, s, flags);
   }

@@ -255,13 +255,19 @@ __device__ inline Folded fold(float x) {
 //   sin: c ^ (a & ~b)   (q1 ^ sr for even q, q1 for odd q)
 //   cos: c ^ (b & ~a)   (q1 for even q, q1 ^ 1 ^ sr for odd q)
 //   tan: a ^ b
+// Written as the v_bitop3_b32 truth tables (bit i of the table is the
+// result for the input bits a b c = i, a most significant), so that the
+// negated operand costs no separate v_not: the compiler otherwise shifts a
+// negated q, and only bit 31 of any of these words is used.
+//   sin: b ^ (a & ~c) = 0x9c,  cos: b ^ (c & ~a) = 0xc6
+// with a = hr, b = q << 30, c = q << 31.
 template <class F>
 __device__ inline uint32_t sin_mask(const F &f) {
-  return (f.q << 30) ^ (f.hr & ~(f.q << 31));
+  return __builtin_amdgcn_bitop3_b32(f.hr, f.q << 30, f.q << 31, 0x9c);
 }
 template <class F>
 __device__ inline uint32_t cos_mask(const F &f) {
-  return (f.q << 30) ^ ((f.q << 31) & ~f.hr);
+  return __builtin_amdgcn_bitop3_b32(f.hr, f.q << 30, f.q << 31, 0xc6);
 }
 template <class F>
 __device__ inline uint32_t tan_mask(const F &f) { return f.hr ^ (f.q << 31); }
@@ -323,9 +329,13 @@ struct FoldedL {
   __device__ float abs_r() const { return ar; }
 };
 
+// MAY_BE_LARGE false: the caller's inputs are below 2^16 or not finite (FP16
+// storage); +-Inf and NaN then give NaN r, t and forms, and the row (the
+// conversion of NaN is 0, the family bit is one bit) stays in the table.
+template <bool MAY_BE_LARGE = true>
 __device__ inline Forms fold_forms_f32(float x, const Tables16 &tb, FoldedL &f) {
   float t;
-  if (__builtin_expect(__builtin_fabsf(x) < kSmall16, 1)) {
+  if (!MAY_BE_LARGE || __builtin_expect(__builtin_fabsf(x) < kSmall16, 1)) {
     const float qb = __builtin_fmaf(x, kTwoOverPiF, kRoundMagicF);
     const float qf = qb - kRoundMagicF;
     float r = __builtin_fmaf(-qf, kPio2F1, x);
