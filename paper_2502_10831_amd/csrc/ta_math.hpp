@@ -35,6 +35,7 @@ constexpr double kPio2Lo = 0x1.1a62633145c07p-54;     // RN(pi/2 - kPio2Hi)
 constexpr double kDegPerRad = 0x1.ca5dc1a63c1f8p+5;   // RN(180/pi)
 constexpr double kRoundMagic = 0x1.8p52;              // 1.5 * 2^52
 constexpr float kLargeArg = 0x1p29f;  // |x| at and above: bit-table reduction
+constexpr float kRoundMagicF = 0x1.8p23f;  // 1.5 * 2^23 (FP32 rounding)
 
 // Bits 1..256 of the binary expansion of 2/pi, most significant first.
 __constant__ uint32_t kTwoOverPiBits[8] = {
@@ -90,7 +91,7 @@ __host__ __device__ constexpr double kdet_of_row(int idx) {
 struct Lin {
   double i, s;  // value = i + s t
 };
-struct LinF {
+struct alignas(16) LinF {  // one 16-byte LDS read per row
   float iN, sN, iD, sD;
 };
 
@@ -129,6 +130,10 @@ struct TablesBwd : TablesFwd {
 struct Tables16 {
   LinF f[8];
   float kdet[8];
+  // 1.5 2^23 for the rounding of x 2/pi, read once into a register: an FMA
+  // with a register addend and a scalar factor is one instruction, where two
+  // immediate operands cost a copy per element.
+  float magic;
   static constexpr bool kUsed = true;
   __device__ static void init(Tables16 &tb) {
     if (threadIdx.x == 0) {
@@ -138,6 +143,7 @@ struct Tables16 {
         tb.f[i] = LinF{float(r.iN), float(r.sN), float(r.iD), float(r.sD)};
         tb.kdet[i] = float(kdet_of_row(i));
       }
+      tb.magic = kRoundMagicF;
     }
   }
 };
@@ -319,7 +325,6 @@ constexpr float kPio2F2 = 0x1.4442d0p-24f;     // RD24(pi/2 - F1)
 constexpr float kPio2F3 = 0x1.84698ap-48f;     // RN24(pi/2 - F1 - F2)
 constexpr float kDegPerRadF = 0x1.ca5dc2p+5f;  // RN24(180/pi)
 constexpr float kSmall16 = 0x1p16f;
-constexpr float kRoundMagicF = 0x1.8p23f;      // 1.5 * 2^23
 
 struct FoldedL {
   uint32_t q;    // quadrant, low bits
@@ -334,20 +339,21 @@ struct FoldedL {
 // conversion of NaN is 0, the family bit is one bit) stays in the table.
 template <bool MAY_BE_LARGE = true>
 __device__ inline Forms fold_forms_f32(float x, const Tables16 &tb, FoldedL &f) {
-  float t;
-  if (!MAY_BE_LARGE || __builtin_expect(__builtin_fabsf(x) < kSmall16, 1)) {
-    const float qb = __builtin_fmaf(x, kTwoOverPiF, kRoundMagicF);
-    const float qf = qb - kRoundMagicF;
-    float r = __builtin_fmaf(-qf, kPio2F1, x);
-    r = __builtin_fmaf(-qf, kPio2F2, r);
-    r = __builtin_fmaf(-qf, kPio2F3, r);
-    f.q = __float_as_uint(qb);  // 2^22 + q in the mantissa: low bits of q
-    f.hr = __float_as_uint(r);
-    f.ar = __builtin_fabsf(r);
-    t = f.ar * kDegPerRadF;
-    f.row = ((f.q << 2) & 4u) | uint32_t(t * (1.0f / 15.0f));
-  } else {
-    const Folded g = fold(x);  // |x| >= 2^16 (BF16), +-Inf, NaN
+  // The FP32 fold on every lane; lanes with |x| >= 2^16, +-Inf or NaN then
+  // overwrite it with the FP64 fold (a rare branch with no else side, so a
+  // wave without such lanes only tests and skips it).
+  const float qb = __builtin_fmaf(x, kTwoOverPiF, tb.magic);
+  const float qf = qb - kRoundMagicF;
+  float r = __builtin_fmaf(-qf, kPio2F1, x);
+  r = __builtin_fmaf(-qf, kPio2F2, r);
+  r = __builtin_fmaf(-qf, kPio2F3, r);
+  f.q = __float_as_uint(qb);  // 2^22 + q in the mantissa: low bits of q
+  f.hr = __float_as_uint(r);
+  f.ar = __builtin_fabsf(r);
+  float t = f.ar * kDegPerRadF;
+  f.row = ((f.q << 2) & 4u) | uint32_t(t * (1.0f / 15.0f));
+  if (MAY_BE_LARGE && __builtin_expect(!(__builtin_fabsf(x) < kSmall16), 0)) {
+    const Folded g = fold(x);
     f.q = g.q;
     f.hr = g.hr;
     f.row = g.row;
