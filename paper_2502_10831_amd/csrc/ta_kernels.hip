@@ -155,7 +155,7 @@ struct FwdOp {
       const Forms v = fold_forms_f32<!SMALL>(in[0], tb, f);
       finish(f, v, out);
     } else {
-      const Folded f = fold(in[0]);
+      const Folded f = fold(in[0], tb.magic);
       finish(f, forms(f, tb), out);
     }
   }
@@ -247,7 +247,7 @@ struct BwdOp {
       const Forms v = fold_forms_f32<!SMALL>(in[0], tb, f);
       finish(f, v, in, out, tb);
     } else {
-      const Folded f = fold(in[0]);
+      const Folded f = fold(in[0], tb.magic);
       finish(f, forms(f, tb), in, out, tb);
     }
   }
@@ -319,7 +319,7 @@ struct SinCosBwdOp {
       const Forms v = fold_forms_f32<!SMALL>(in[0], tb, f);
       finish(f, v, in, out, tb);
     } else {
-      const Folded f = fold(in[0]);
+      const Folded f = fold(in[0], tb.magic);
       finish(f, forms(f, tb), in, out, tb);
     }
   }

@@ -100,6 +100,7 @@ struct alignas(16) LinF {  // one 16-byte LDS read per row
 // the 16-bit kernels the FP32 rows and the FP32 factors.
 struct TablesFwd {
   Lin n[8], d[8];
+  double magic;  // 1.5 2^52, the rounding constant of the reduction
   static constexpr bool kUsed = true;
   __device__ static void fill(TablesFwd &tb) {
 #pragma unroll
@@ -108,6 +109,7 @@ struct TablesFwd {
       tb.n[i] = Lin{r.iN, r.sN};
       tb.d[i] = Lin{r.iD, r.sD};
     }
+    tb.magic = kRoundMagic;
   }
   __device__ static void init(TablesFwd &tb) {
     if (threadIdx.x == 0) fill(tb);
@@ -207,15 +209,18 @@ __device__ inline void reduce_large(float x, double &r, uint32_t &q) {
   q = qq;
 }
 
-// r and the low bits of q (two's complement) for any float x.
-__device__ inline void reduce(float x, double &r, uint32_t &q) {
+// r and the low bits of q (two's complement) for any float x.  `magic` is
+// 1.5 2^52; kernels pass it from their LDS table, so that it sits in a
+// register and the rounding of x 2/pi is one FMA (with it as an immediate
+// the compiler copies it into the accumulator for every element).
+__device__ inline void reduce(float x, double &r, uint32_t &q,
+                              double magic = kRoundMagic) {
   const double xd = double(x);
-  // q = round(x 2/pi) by adding 1.5 2^52 (the product is rounded first: an
-  // x within an ulp of a half-integer multiple of pi/4 may get the other
-  // neighbour and |r| up to pi/4 (1 + 2^-50), where pieces 2 and 3 meet
-  // continuously).  A single FMA would need the 64-bit constant copied into
-  // its accumulator register first: no fewer instructions.
-  const double qb = xd * kTwoOverPi + kRoundMagic;
+  // q = the integer nearest x RN(2/pi), by one FMA adding 1.5 2^52 (the
+  // rounding of 2/pi can give the other neighbour for an x next to an odd
+  // multiple of pi/4, and |r| then exceeds pi/4 by at most |x| 2^-54 pi/2:
+  // pieces 2 and 3 meet continuously there and slot 3 continues both).
+  const double qb = __builtin_fma(xd, kTwoOverPi, magic);
   const double qd = qb - kRoundMagic;  // +0 when q = 0, so r keeps x's zero
   q = uint32_t(__double2loint(qb));    // low word of the mantissa = q
   double rr = __builtin_fma(-qd, kPio2Hi, xd);  // exact
@@ -244,9 +249,9 @@ struct Folded {
   __device__ double abs_r() const { return __builtin_fabs(r); }
 };
 
-__device__ inline Folded fold(float x) {
+__device__ inline Folded fold(float x, double magic = kRoundMagic) {
   Folded f;
-  reduce(x, f.r, f.q);
+  reduce(x, f.r, f.q, magic);
   f.hr = uint32_t(__double2hiint(f.r));
   f.t = f.abs_r() * kDegPerRad;  // the abs folds into the multiply
   // j = 15-degree slot of |r|; the family (q & 1) selects slots 4..6
