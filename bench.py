@@ -273,10 +273,36 @@ def comparators(x, x_host, n, args, torch, ta, np):
                 e[f"{name}_max_abs"] = float(np.abs(g - ref[name]).max())
         return e
 
+    def stats(outs):
+        """The paper's accuracy statistics (Section 3 benchmark): mean, max
+        and standard deviation of the absolute and relative error against
+        FP64 libm, the relative error taken as 0 where |ref| <= 1e-12."""
+        st = {}
+        for name, t in outs.items():
+            g = t[it].double().cpu().numpy()
+            r = ref[name]
+            ok = np.isfinite(r) & np.isfinite(g)
+            ae = np.abs(g - r)[ok]
+            big = np.abs(r[ok]) > 1e-12
+            re = np.where(big, ae / np.where(big, np.abs(r[ok]), 1.0), 0.0)
+            st[name] = {"abs_mean": float(ae.mean()), "abs_max": float(ae.max()),
+                        "abs_std": float(ae.std()), "rel_mean": float(re.mean()),
+                        "rel_max": float(re.max()), "rel_std": float(re.std())}
+        return st
+
     ys, yc, yt = (torch.empty_like(x) for _ in range(3))
     ta.ta_sincos(x, ys, yc, yt)
-    res["ta_sincos_tan"] = {"error_vs_libm": errors({"sin": ys, "cos": yc,
-                                                      "tan": yt})}
+    outs = {"sin": ys, "cos": yc, "tan": yt}
+    # inputs whose fold angle lies within 2.5e-7 rad of a jump node (15, 30,
+    # 60, 75 degrees), where either neighbouring piece is a correct result
+    rho = np.arcsin(np.minimum(np.abs(np.sin(xs)), 1.0))
+    step = math.pi / 12
+    knode = np.rint(rho / step)
+    band = (np.abs(rho - knode * step) < 2.5e-7) & np.isin(knode, (1, 2, 4, 5))
+    res["ta_sincos_tan"] = {"error_vs_libm": errors(outs),
+                            "accuracy_stats_vs_libm": stats(outs),
+                            "sample": "2^20 random elements of the workload",
+                            "jump_band_elements_in_sample": int(band.sum())}
     for kind, label in ((0, "builtin_sinf_cosf_tanf"),
                         (1, "builtin___sinf___cosf___tanf")):
         def f(kind=kind):

@@ -50,14 +50,25 @@ extern "C" {
 /* TA_F64: FP64 storage, and every stage of the method in FP64 (the paper's
  * own functions take and return double).  Results agree with an exact
  * evaluation of the same formulas to within 6 FP64 ulp. */
-typedef enum { TA_F32 = 0, TA_F16 = 1, TA_BF16 = 2, TA_F64 = 3 } ta_dtype;
+/* The last enumerator of each enum only widens its range to every 32-bit
+ * value, so that any int a caller passes is a valid value of the type (an
+ * unknown dtype is then an error status, not undefined behaviour in the
+ * library's C++); it is not a dtype or a status. */
+typedef enum {
+  TA_F32 = 0,
+  TA_F16 = 1,
+  TA_BF16 = 2,
+  TA_F64 = 3,
+  TA_DTYPE_RANGE_ = 0x7fffffff
+} ta_dtype;
 
 typedef enum {
   TA_OK = 0,
   TA_EINVAL = 1,
   TA_EDTYPE = 2,
   TA_EOVERLAP = 3,
-  TA_EHIP = 4
+  TA_EHIP = 4,
+  TA_STATUS_RANGE_ = 0x7fffffff
 } ta_status;
 
 /* Flag bits for the *_ex forward calls. */

@@ -787,6 +787,7 @@ hipError_t launch_dtype(ta_dtype dt, const void *const *in, void *const *out,
     case TA_F16: return launch_map<F16, typename Op::LowH>(in, out, n, s, flags);
     case TA_BF16: return launch_map<BF16, typename Op::Low>(in, out, n, s, flags);
     case TA_F64: return launch_map<F64, Op>(in, out, n, s, flags);
+    default: break;
   }
   return hipErrorInvalidValue;
 }
@@ -1116,6 +1117,7 @@ ta_status ta_sincos_encode(const void *x, void *y, int64_t n, int nfreq,
     case TA_F16: e = launch_encode<F16>(x, y, n, nfreq, s); break;
     case TA_BF16: e = launch_encode<BF16>(x, y, n, nfreq, s); break;
     case TA_F64: e = launch_encode<F64>(x, y, n, nfreq, s); break;
+    default: break;
   }
   return finish(e);
 }
@@ -1127,6 +1129,7 @@ const char *ta_status_str(ta_status st) {
     case TA_EDTYPE: return "TA_EDTYPE: unsupported dtype";
     case TA_EOVERLAP: return "TA_EOVERLAP: output partially overlaps another buffer";
     case TA_EHIP: return "TA_EHIP: HIP launch failed";
+    default: break;
   }
   return "unknown ta_status";
 }
