@@ -441,7 +441,78 @@ def extras(args, torch, ta, dev):
                        "g ~ N(0, 1)")
     del x, g, y, gx
     res.update(other_workloads(args, torch, ta, dev))
+    log("paper protocol (1000 angles, FP64 and FP32)")
+    res["paper_protocol_fp64"] = paper_protocol(torch, ta, dev, torch.float64)
+    res["paper_protocol_fp32"] = paper_protocol(torch, ta, dev, torch.float32)
     return res
+
+
+def paper_protocol(torch, ta, dev, dtype=None, n_angles=1000, copies=1 << 22,
+                   reps=3):
+    """The run_benchmark loop of Section 3 on the GPU, in the paper's
+    precision (FP64) or FP32: 1000 angles from U[-1e6, 1e6] (NumPy PCG64, seed
+    2024873); for each angle an array of `copies` copies of it (32 MiB, so
+    input and output stay in the 256 MB Infinity Cache and a launch measures
+    the arithmetic of that angle's path more than HBM), the median of `reps`
+    launches of the device library's function (torch.sin / cos / tan) and of
+    each method (the proposed function evaluated to FP64 accuracy, the
+    paper's literal arithmetic with its fast inverse square root, Taylor-5/7/9);
+    the speed-up ratio of
+    an angle is library time over method time.  Reported per function: the
+    mean speed-up ratio over the angles and the wins (angles where the method
+    was faster), the two speed rows of Tables 1-3."""
+    import numpy as np
+    angles = np.random.default_rng(2024873).uniform(-1e6, 1e6, n_angles)
+    dtype = dtype or torch.float64
+    x = torch.empty(copies, dtype=dtype, device=dev)
+    y = torch.empty_like(x)
+    variants = {
+        "sin": (lambda: torch.sin(x, out=y), lambda: ta.ta_sin(x, y),
+                lambda: ta.ta_paper_sincos(x, ys=y), ta.ta_taylor_sin),
+        "cos": (lambda: torch.cos(x, out=y), lambda: ta.ta_cos(x, y),
+                lambda: ta.ta_paper_sincos(x, yc=y), ta.ta_taylor_cos),
+        "tan": (lambda: torch.tan(x, out=y), lambda: ta.ta_tan(x, y),
+                lambda: ta.ta_paper_sincos(x, yt=y), ta.ta_taylor_tan)}
+    fns = []
+    for name, (std, prop, lit, tay) in variants.items():
+        fns.append((name, "std", std))
+        fns.append((name, "proposed", prop))
+        fns.append((name, "paper_fisr", lit))
+        for t in (5, 7, 9):
+            fns.append((name, f"taylor{t}", lambda tay=tay, t=t: tay(x, y, t)))
+    x.fill_(1.0)
+    time_launches(lambda: [f() for _, _, f in fns], 1, 3, torch, WARM_S)
+    times = {(n, v): [] for n, v, _ in fns}
+    for a in angles:
+        x.fill_(float(a))
+        ev = []
+        for n, v, f in fns:
+            for _ in range(reps):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                f()
+                e1.record()
+                ev.append((n, v, e0, e1))
+        torch.cuda.synchronize()
+        per = {}
+        for n, v, e0, e1 in ev:
+            per.setdefault((n, v), []).append(e0.elapsed_time(e1))
+        for k, ts in per.items():
+            times[k].append(float(np.median(ts)))
+    out = {"angles": n_angles, "copies_per_angle": copies,
+           "std": f"torch.sin / torch.cos / torch.tan in {dtype} (device library)"}
+    for name in variants:
+        std = np.array(times[(name, "std")])
+        row = {"std_mean_us": round(float(std.mean()) * 1e3, 2)}
+        for v in ("proposed", "paper_fisr", "taylor5", "taylor7", "taylor9"):
+            t = np.array(times[(name, v)])
+            row[v] = {"mean_speedup": round(float((std / t).mean()), 3),
+                      "wins": int((t < std).sum()),
+                      "mean_us": round(float(t.mean()) * 1e3, 2)}
+        out[name] = row
+    del x, y
+    return out
 
 
 def sq_per_elem():
