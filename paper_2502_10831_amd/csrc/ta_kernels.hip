@@ -449,6 +449,7 @@ template <int NI, int NO>
 struct CopyOp {
   static constexpr int NIN = NI;
   static constexpr int NOUT = NO;
+  static constexpr bool kIsCopy = true;  // launched with the copy shape
   using Table = NoTable;
   using Low = CopyOp;
   using LowH = CopyOp;
@@ -506,9 +507,22 @@ struct Shape {
 #ifndef TA_SHAPE_HALF_TWOIN
 #define TA_SHAPE_HALF_TWOIN {128, 4, true, true}
 #endif
+// The copy comparators (the HBM ceiling a kernel is compared with): one
+// wave per workgroup, the fastest plain copy of 1 -> 3 and 2 -> 2 FP32
+// arrays measured on MI355X (about 2 % above 256 threads).
+#ifndef TA_SHAPE_COPY
+#define TA_SHAPE_COPY {64, 1, false, true}
+#endif
+
+template <class Op, class = void>
+struct is_copy : std::false_type {};
+template <class Op>
+struct is_copy<Op, std::void_t<decltype(Op::kIsCopy)>> : std::true_type {};
 
 template <class ST, class Op>
 constexpr Shape shape_for() {
+  if (sizeof(typename ST::raw) >= 4 && is_copy<Op>::value)
+    return Shape TA_SHAPE_COPY;
   if (sizeof(typename ST::raw) == 2)
     return Op::NIN >= 2 ? Shape TA_SHAPE_HALF_TWOIN : Shape TA_SHAPE_HALF;
   if (Op::NIN >= 2)

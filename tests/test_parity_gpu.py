@@ -776,6 +776,19 @@ def test_comparators_and_copy(dev):
     ta.ta_copy([xd], outs)
     for o in outs:
         assert torch.equal(o, xd)
+    # the copy shapes of the ceilings (1 -> 1, 2 -> 2) with ragged sizes,
+    # an unaligned start and canaries after the end
+    for n in ((1 << 20) + 5, 1000003):
+        a = torch.randn(n + 1, device=dev)[1:]
+        b = torch.randn(n, device=dev, dtype=torch.float64).float()
+        ya = torch.full((n + 8,), 7.0, device=dev)
+        yb = torch.full((n + 8,), 7.0, device=dev)
+        ta.ta_copy([a], [ya[:n]])
+        assert torch.equal(ya[:n], a) and bool((ya[n:] == 7.0).all())
+        ya.fill_(7.0)
+        ta.ta_copy([a, b], [ya[:n], yb[:n]])
+        assert torch.equal(ya[:n], a) and torch.equal(yb[:n], b)
+        assert bool((ya[n:] == 7.0).all()) and bool((yb[n:] == 7.0).all())
 
 
 def test_force_fp32_reduction_flag(dev):
