@@ -34,16 +34,34 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+_C_TOKENS = None
+
+
+def _code_only(text: str) -> str:
+    """C/C++/HIP source without its comments and with whitespace collapsed
+    (string and character literals kept), so that a comment edit does not
+    count as a change of the compiled code."""
+    import re
+    global _C_TOKENS
+    if _C_TOKENS is None:
+        _C_TOKENS = re.compile(r'//[^\n]*|/\*.*?\*/|"(?:\\.|[^"\\])*"'
+                               r"|'(?:\\.|[^'\\])*'", re.S)
+    kept = _C_TOKENS.sub(lambda m: " " if m.group(0)[0] == "/" else m.group(0),
+                         text)
+    return " ".join(kept.split())
+
+
 def source_hash() -> str:
-    """Hash of the kernel sources and the header they compile against."""
+    """Hash of the kernel sources and the header they compile against,
+    comments and whitespace aside."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2502_10831_amd", "csrc")
     paths = [os.path.join(csrc, name) for name in sorted(os.listdir(csrc))]
     paths.append(os.path.join(ROOT, "include", "ta.h"))
     for path in paths:
-        with open(path, "rb") as f:
+        with open(path, encoding="utf-8") as f:
             h.update(os.path.basename(path).encode())
-            h.update(f.read())
+            h.update(_code_only(f.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -2,9 +2,10 @@
 // approximations (Goyal & Arora, arXiv 2502.10831) for gfx950.
 //
 // Split of the work (one element):
-//   1. Argument reduction, FP64.  x = q*(pi/2) + r, |r| <= pi/4 (FP64
-//      Cody-Waite with a two-word pi/2 below 2^29; a 2/pi bit-table reduction
-//      above).  a = |r| in degrees gives the piece inside [0, 45]; the parity
+//   1. Argument reduction, FP64.  x = q*(pi/2) + r, |r| <= pi/4 up to the
+//      rounding of 2/pi in q (FP64 Cody-Waite with a two-word pi/2 below
+//      2^29; a 2/pi bit-table reduction above).  a = |r| in degrees gives the
+//      piece inside [0, 45] (slot 3 of the table takes the excess); the parity
 //      of q says whether the fold angle is rho = a (q even) or its complement
 //      (q odd, rho = 90 - a degrees).  This is the Section 3 fold
 //      rho = arcsin|sin x|, with the sign of each output from (q mod 4, sign r).
@@ -14,7 +15,9 @@
 //      with no cancellation at the pole.  FP64 FMA issues at the same rate as
 //      unpacked FP32 FMA on gfx950, so this costs no more than an FP32
 //      reduction with a carried residual and rounds N and D only once.
-//   3. Everything after is FP32: Q = N^2 + D^2 (Appendix A.4), an inverse
+//   3. Everything after is FP32 (16-bit storage runs steps 1 and 2 in FP32
+//      as well; FP64 storage runs every step in FP64, further below):
+//      Q = N^2 + D^2 (Appendix A.4), an inverse
 //      square root (v_rsq_f32 plus one Newton step whose residual is computed
 //      exactly with FMAs), sin = N*y, cos = D*y, and tan = N/D as a reciprocal
 //      plus one exact-residual correction.
@@ -241,8 +244,8 @@ __device__ inline uint32_t slot_of(double t) {
 }
 
 struct Folded {
-  double r;       // reduced argument, |r| <= pi/4 (use abs_r())
-  double t;       // |r| in degrees, [0, 45]
+  double r;       // reduced argument, |r| <= pi/4 (+ q's rounding; abs_r())
+  double t;       // |r| in degrees, [0, 45] (+ the same excess, slot 3)
   uint32_t q;     // quadrant, low bits
   uint32_t hr;    // high word of r: bit 31 = sign of r
   uint32_t row;   // LDS table slot j + 4*(q & 1)
