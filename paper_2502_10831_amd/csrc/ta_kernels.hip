@@ -180,7 +180,7 @@ struct FwdOp {
   __device__ static void apply(const double *in, double *out, const Table &tb,
                                uint32_t) {
     static_assert(!kFp32Fold, "FP64 storage uses the FP64 table");
-    const Folded64 f = fold64(in[0]);
+    const Folded64 f = fold64(in[0], tb.magic);
     const Forms64 v = forms64(f, tb);
     int o = 0;
     if constexpr ((MASK & (kSin | kCos)) != 0) {
@@ -277,7 +277,7 @@ struct BwdOp {
   }
   __device__ static void apply(const double *in, double *out, const Table &tb,
                                uint32_t) {
-    const Folded64 f = fold64(in[0]);
+    const Folded64 f = fold64(in[0], tb.magic);
     const Forms64 v = forms64(f, tb);
     const double kdet = tb.kdet64[f.row];
     if constexpr (WHICH == kTan) {
@@ -337,7 +337,7 @@ struct SinCosBwdOp {
   }
   __device__ static void apply(const double *in, double *out, const Table &tb,
                                uint32_t) {
-    const Folded64 f = fold64(in[0]);
+    const Folded64 f = fold64(in[0], tb.magic);
     const Forms64 v = forms64(f, tb);
     const double y = rsqrt64_refined(v.q);
     const double omega = tb.kdet64[f.row] * y * y;

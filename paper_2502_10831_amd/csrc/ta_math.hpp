@@ -474,7 +474,6 @@ __device__ inline float taylor_tan_unsigned(float rho) {
 // ---------------------------------------------------------------------------
 constexpr double kPio2Lo2 = -0x1.f1976b7ed8fbcp-110;   // RN(pi/2 - Hi - Lo)
 constexpr double kDegPerRadLo = -0x1.1e7ab456405f9p-49;  // RN(180/pi - kDegPerRad)
-constexpr double kPio4 = 0x1.921fb54442d18p-1;          // RN(pi/4)
 constexpr double kLargeArg64 = 0x1p29;
 
 // Bits of 2/pi for the FP64 bit-table reduction: word 0 is zero (bits -31
@@ -590,8 +589,15 @@ __device__ inline void reduce_large64(double x, double &rh, double &rl,
 }
 
 // x = q pi/2 + rh + rl for any double x.
-__device__ inline void reduce64(double x, double &rh, double &rl, uint32_t &q) {
-  const double qb = x * kTwoOverPi + kRoundMagic;
+__device__ inline void reduce64(double x, double &rh, double &rl, uint32_t &q,
+                                double magic = kRoundMagic) {
+  // q: the integer nearest x RN(2/pi), one FMA with 1.5 2^52 (`magic`, from
+  // the kernel's LDS table, so that it sits in a register).  The rounding of
+  // 2/pi can make q the neighbour of the nearest quadrant next to an odd
+  // multiple of pi/4; |r| then exceeds pi/4 by at most |x| 2^-54 pi/2
+  // (2^-24 below 2^29), and slot 3 of the table continues both quadrant
+  // families there, so r needs no correction.
+  const double qb = __builtin_fma(x, kTwoOverPi, magic);
   const double qd = qb - kRoundMagic;
   q = uint32_t(__double2loint(qb));
   const double r1 = __builtin_fma(-qd, kPio2Hi, x);  // exact
@@ -604,16 +610,6 @@ __device__ inline void reduce64(double x, double &rh, double &rl, uint32_t &q) {
   rh = __builtin_copysign(rh, s);  // keeps the sign of a zero x
   if (__builtin_expect(__builtin_fabs(x) >= kLargeArg64, 0))
     reduce_large64(x, rh, rl, q);
-  // x 2/pi is rounded before q is: q may be the neighbour of the nearest
-  // quadrant, leaving |r| a little above pi/4; move r into range
-  // (rh - Hi is exact there, by Sterbenz's lemma).
-  if (__builtin_expect(__builtin_fabs(rh) > kPio4, 0)) {
-    const double sg = rh > 0.0 ? 1.0 : -1.0;
-    const double h = rh - sg * kPio2Hi;
-    const double l = __builtin_fma(-sg, kPio2Lo2, rl - sg * kPio2Lo);
-    fast_two_sum(h, l, rh, rl);
-    q += rh < 0.0 ? 1u : 0xffffffffu;  // sign of the new r is opposite
-  }
 }
 
 struct Folded64 {
@@ -627,9 +623,9 @@ struct Folded64 {
   __device__ double abs_rl() const { return flip_sign(rl, hr); }
 };
 
-__device__ inline Folded64 fold64(double x) {
+__device__ inline Folded64 fold64(double x, double magic = kRoundMagic) {
   Folded64 f;
-  reduce64(x, f.rh, f.rl, f.q);
+  reduce64(x, f.rh, f.rl, f.q, magic);
   f.hr = uint32_t(__double2hiint(f.rh));
   const double ra = f.abs_r();
   f.t = __builtin_fma(ra, kDegPerRad,

@@ -34,13 +34,12 @@ def test_reduction_constants(text):
     assert _const(text, "kDegPerRad") == float(180 / pi)
     assert _const(text, "kRoundMagic") == 1.5 * 2.0 ** 52
     assert _const(text, "kPi12") == float(pi / 12)
-    # FP64 path: third word of pi/2, the low word of 180/pi, pi/4
+    # FP64 path: third word of pi/2, the low word of 180/pi
     lo = _const(text, "kPio2Lo")
     assert _const(text, "kPio2Lo2") == float(pi / 2 - mpmath.mpf(hi) -
                                              mpmath.mpf(lo))
     k = _const(text, "kDegPerRad")
     assert _const(text, "kDegPerRadLo") == float(180 / pi - mpmath.mpf(k))
-    assert _const(text, "kPio4") == float(pi / 4)
     assert _const(text, "kLargeArg64") == 2.0 ** 29
 
 
