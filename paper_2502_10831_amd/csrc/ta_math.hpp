@@ -212,23 +212,29 @@ __device__ inline void reduce_large(float x, double &r, uint32_t &q) {
   q = qq;
 }
 
-// r and the low bits of q (two's complement) for any float x.  `magic` is
-// 1.5 2^52; kernels pass it from their LDS table, so that it sits in a
-// register and the rounding of x 2/pi is one FMA (with it as an immediate
-// the compiler copies it into the accumulator for every element).
-__device__ inline void reduce(float x, double &r, uint32_t &q,
-                              double magic = kRoundMagic) {
+// r and the low bits of q (two's complement) for any float x, given
+// qb = x RN(2/pi) + 1.5 2^52 rounded (q = the integer in the low mantissa
+// bits; the rounding of 2/pi can give the neighbour of the nearest quadrant
+// for an x next to an odd multiple of pi/4, and |r| then exceeds pi/4 by at
+// most |x| 2^-54 pi/2: pieces 2 and 3 meet continuously there and slot 3
+// of the table continues both quadrant families).
+__device__ inline void reduce_from(float x, double qb, double &r, uint32_t &q) {
   const double xd = double(x);
-  // q = the integer nearest x RN(2/pi), by one FMA adding 1.5 2^52 (the
-  // rounding of 2/pi can give the other neighbour for an x next to an odd
-  // multiple of pi/4, and |r| then exceeds pi/4 by at most |x| 2^-54 pi/2:
-  // pieces 2 and 3 meet continuously there and slot 3 continues both).
-  const double qb = __builtin_fma(xd, kTwoOverPi, magic);
   const double qd = qb - kRoundMagic;  // +0 when q = 0, so r keeps x's zero
   q = uint32_t(__double2loint(qb));    // low word of the mantissa = q
   double rr = __builtin_fma(-qd, kPio2Hi, xd);  // exact
   r = __builtin_fma(-qd, kPio2Lo, rr);
   if (__builtin_expect(__builtin_fabsf(x) >= kLargeArg, 0)) reduce_large(x, r, q);
+}
+// Kernels with an LDS table pass 1.5 2^52 from it: held in a register, the
+// rounding is one FMA.
+__device__ inline void reduce(float x, double &r, uint32_t &q, double magic) {
+  reduce_from(x, __builtin_fma(double(x), kTwoOverPi, magic), r, q);
+}
+// Table-less kernels: a product and an add, both constants from scalar
+// registers (one FMA would take a per-element copy of the 64-bit addend).
+__device__ inline void reduce(float x, double &r, uint32_t &q) {
+  reduce_from(x, double(x) * kTwoOverPi + kRoundMagic, r, q);
 }
 
 // Folded element: everything the later stages need.
@@ -252,15 +258,23 @@ struct Folded {
   __device__ double abs_r() const { return __builtin_fabs(r); }
 };
 
-__device__ inline Folded fold(float x, double magic = kRoundMagic) {
-  Folded f;
-  reduce(x, f.r, f.q, magic);
+__device__ inline Folded fold_finish(Folded f) {
   f.hr = uint32_t(__double2hiint(f.r));
   f.t = f.abs_r() * kDegPerRad;  // the abs folds into the multiply
   // j = 15-degree slot of |r|; the family (q & 1) selects slots 4..6
   const uint32_t j = slot_of(f.t);
   f.row = ((f.q << 2) & 4u) | j;
   return f;
+}
+__device__ inline Folded fold(float x, double magic) {
+  Folded f;
+  reduce(x, f.r, f.q, magic);
+  return fold_finish(f);
+}
+__device__ inline Folded fold(float x) {
+  Folded f;
+  reduce(x, f.r, f.q);
+  return fold_finish(f);
 }
 
 // Output signs as bit 31 of a word (other bits are don't-care).  With
@@ -589,15 +603,14 @@ __device__ inline void reduce_large64(double x, double &rh, double &rl,
 }
 
 // x = q pi/2 + rh + rl for any double x.
-__device__ inline void reduce64(double x, double &rh, double &rl, uint32_t &q,
-                                double magic = kRoundMagic) {
-  // q: the integer nearest x RN(2/pi), one FMA with 1.5 2^52 (`magic`, from
-  // the kernel's LDS table, so that it sits in a register).  The rounding of
-  // 2/pi can make q the neighbour of the nearest quadrant next to an odd
-  // multiple of pi/4; |r| then exceeds pi/4 by at most |x| 2^-54 pi/2
-  // (2^-24 below 2^29), and slot 3 of the table continues both quadrant
-  // families there, so r needs no correction.
-  const double qb = __builtin_fma(x, kTwoOverPi, magic);
+// qb = x RN(2/pi) + 1.5 2^52 rounded, q in its low mantissa bits (one FMA
+// with the constant from a kernel's LDS table, else a product and an add, as
+// for FP32 inputs).  The rounding of 2/pi can make q the neighbour of the
+// nearest quadrant next to an odd multiple of pi/4; |r| then exceeds pi/4 by
+// at most |x| 2^-54 pi/2 (2^-24 below 2^29), and slot 3 of the table
+// continues both quadrant families there, so r needs no correction.
+__device__ inline void reduce64_from(double x, double qb, double &rh, double &rl,
+                                     uint32_t &q) {
   const double qd = qb - kRoundMagic;
   q = uint32_t(__double2loint(qb));
   const double r1 = __builtin_fma(-qd, kPio2Hi, x);  // exact
@@ -611,6 +624,13 @@ __device__ inline void reduce64(double x, double &rh, double &rl, uint32_t &q,
   if (__builtin_expect(__builtin_fabs(x) >= kLargeArg64, 0))
     reduce_large64(x, rh, rl, q);
 }
+__device__ inline void reduce64(double x, double &rh, double &rl, uint32_t &q,
+                                double magic) {
+  reduce64_from(x, __builtin_fma(x, kTwoOverPi, magic), rh, rl, q);
+}
+__device__ inline void reduce64(double x, double &rh, double &rl, uint32_t &q) {
+  reduce64_from(x, x * kTwoOverPi + kRoundMagic, rh, rl, q);
+}
 
 struct Folded64 {
   double rh, rl;  // reduced argument, |rh + rl| <= pi/4
@@ -623,15 +643,23 @@ struct Folded64 {
   __device__ double abs_rl() const { return flip_sign(rl, hr); }
 };
 
-__device__ inline Folded64 fold64(double x, double magic = kRoundMagic) {
-  Folded64 f;
-  reduce64(x, f.rh, f.rl, f.q, magic);
+__device__ inline Folded64 fold64_finish(Folded64 f) {
   f.hr = uint32_t(__double2hiint(f.rh));
   const double ra = f.abs_r();
   f.t = __builtin_fma(ra, kDegPerRad,
                       __builtin_fma(ra, kDegPerRadLo, f.abs_rl() * kDegPerRad));
   f.row = ((f.q << 2) & 4u) | slot_of(f.t);
   return f;
+}
+__device__ inline Folded64 fold64(double x, double magic) {
+  Folded64 f;
+  reduce64(x, f.rh, f.rl, f.q, magic);
+  return fold64_finish(f);
+}
+__device__ inline Folded64 fold64(double x) {
+  Folded64 f;
+  reduce64(x, f.rh, f.rl, f.q);
+  return fold64_finish(f);
 }
 
 struct Forms64 {
