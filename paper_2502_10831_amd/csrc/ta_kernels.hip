@@ -145,6 +145,8 @@ struct FwdOp {
   static constexpr int NOUT = ((MASK & kSin) ? 1 : 0) + ((MASK & kCos) ? 1 : 0) +
                               ((MASK & kTan) ? 1 : 0);
   static constexpr bool kFp32Fold = LOW || F32RED;
+  // the tan guard keeps |r| live to the end: more than 64 VGPRs
+  static constexpr bool kWideSingle = GUARD;
   using Table = typename std::conditional<kFp32Fold, Tables16, TablesFwd>::type;
   using Low = FwdOp<MASK, GUARD, true>;
   using LowH = FwdOp<MASK, GUARD, true, false, true>;
@@ -473,8 +475,12 @@ struct IoPtrs {
 // MI355X (2^27-2^29 elements):
 //   one input, several FP32 or FP64 outputs: 256 threads, one 16-byte access
 //     per stream per thread, nontemporal stores;
-//   one FP32/FP64 output, the method (LDS table): four accesses per thread,
-//     nontemporal loads and stores;
+//   one FP32 output, the method (LDS table): two accesses per thread,
+//     nontemporal loads and stores, and at most 64 VGPRs (eight workgroups
+//     per CU: eight waves per SIMD; 5-6 % above four accesses in 86 VGPRs;
+//     the registers spilled are those of the rare large-argument branch);
+//     one FP64 output, the tan guard or the paper-literal arithmetic:
+//     four accesses;
 //   one FP32/FP64 output, light functors (Taylor, copy): one access;
 //   two FP32/FP64 inputs, one output (backward): 128 threads, two accesses,
 //     nontemporal loads and stores; two outputs (fused forward+backward):
@@ -485,12 +491,16 @@ struct IoPtrs {
 struct Shape {
   int block, unroll;
   bool nt_load, nt_store;
+  int min_blocks = 1;  // __launch_bounds__ minimum workgroups per CU
 };
 #ifndef TA_SHAPE_MULTI
 #define TA_SHAPE_MULTI {256, 1, false, true}
 #endif
 #ifndef TA_SHAPE_SINGLE
-#define TA_SHAPE_SINGLE {256, 4, true, true}
+#define TA_SHAPE_SINGLE {256, 2, true, true, 8}
+#endif
+#ifndef TA_SHAPE_SINGLE_WIDE
+#define TA_SHAPE_SINGLE_WIDE {256, 4, true, true}
 #endif
 #ifndef TA_SHAPE_LIGHT
 #define TA_SHAPE_LIGHT {256, 1, false, true}
@@ -519,6 +529,12 @@ struct is_copy : std::false_type {};
 template <class Op>
 struct is_copy<Op, std::void_t<decltype(Op::kIsCopy)>> : std::true_type {};
 
+template <class Op, class = void>
+struct wide_single : std::false_type {};
+template <class Op>
+struct wide_single<Op, std::void_t<decltype(Op::kWideSingle)>>
+    : std::integral_constant<bool, Op::kWideSingle> {};
+
 template <class ST, class Op>
 constexpr Shape shape_for() {
   if (sizeof(typename ST::raw) >= 4 && is_copy<Op>::value)
@@ -529,7 +545,13 @@ constexpr Shape shape_for() {
     return Op::NOUT == 1 ? Shape TA_SHAPE_TWOIN1 : Shape TA_SHAPE_TWOIN;
   if (Op::NOUT >= 2) return Shape TA_SHAPE_MULTI;
   // the functors that evaluate the method use the LDS table
-  return Op::Table::kUsed ? Shape TA_SHAPE_SINGLE : Shape TA_SHAPE_LIGHT;
+  if (!Op::Table::kUsed) return Shape TA_SHAPE_LIGHT;
+  // FP64 storage and the paper-literal FP64 arithmetic need more than 64
+  // VGPRs: four accesses per thread, no occupancy bound
+  if (sizeof(typename ST::raw) == 8 || wide_single<Op>::value ||
+      std::is_same<typename Op::Table, PaperTables>::value)
+    return Shape TA_SHAPE_SINGLE_WIDE;
+  return Shape TA_SHAPE_SINGLE;
 }
 
 template <bool NT, class V = u32x4>
@@ -566,11 +588,9 @@ __device__ inline void scalar_element(const IoPtrs &io, int64_t i,
 // accesses per stream per thread, all loads issued before any compute.  The
 // workgroup with blockIdx 0 also does the scalar head [0, head) and tail
 // [head + nvec*VEC, n).
-#ifndef TA_MIN_BLOCKS
-#define TA_MIN_BLOCKS 1
-#endif
-template <class ST, class Op, int BLOCK, int UNROLL, bool NTL, bool NTS>
-__global__ __launch_bounds__(BLOCK, TA_MIN_BLOCKS) void map_vec_kernel(IoPtrs io, int64_t head,
+template <class ST, class Op, int BLOCK, int UNROLL, bool NTL, bool NTS,
+          int MINB>
+__global__ __launch_bounds__(BLOCK, MINB) void map_vec_kernel(IoPtrs io, int64_t head,
                                                         int64_t nvec, int64_t n) {
   using raw = typename ST::raw;
   constexpr int VEC = ST::kVec;
@@ -784,7 +804,8 @@ hipError_t launch_map(const void *const *in, void *const *out, int64_t n,
     if (blocks < 1) blocks = 1;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
     return launch(
-        map_vec_kernel<ST, Op, sh.block, sh.unroll, sh.nt_load, sh.nt_store>,
+        map_vec_kernel<ST, Op, sh.block, sh.unroll, sh.nt_load, sh.nt_store,
+                       sh.min_blocks>,
         blocks, sh.block, stream, io, head, nvec, n);
   }
   int64_t blocks = (n + kScalarBlock - 1) / kScalarBlock;
