@@ -1,0 +1,70 @@
+"""bench.py pieces that need no GPU: the refusal of --gpus N > 1, the
+comment-blind source hash that ties profiles to kernel sources, and the
+rocprofv3 trace summary on a synthetic trace."""
+import csv
+import os
+import subprocess
+import sys
+
+import pytest
+
+from conftest import ROOT
+
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"),
+                        "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr or "single" in r.stderr
+
+
+def test_code_only_drops_comments_keeps_strings():
+    src = ('int a = 1; // note\n/* block\n comment */ const char *s = '
+           '"// kept /* kept */"; char c = \'/\';  int   b;\n')
+    out = bench._code_only(src)
+    assert "note" not in out and "block" not in out
+    assert '"// kept /* kept */"' in out and "'/'" in out
+    assert "int b;" in out
+    assert bench._code_only("x = 1; // a") == bench._code_only("x  =  1;")
+
+
+def test_source_hash_is_stable_and_tracks_code():
+    h = bench.source_hash()
+    assert len(h) == 16 and h == bench.source_hash()
+
+
+def _write_trace(path, rows):
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Kernel_Name", "Grid_Size_X",
+                                          "Start_Timestamp", "End_Timestamp"])
+        w.writeheader()
+        w.writerows(rows)
+
+
+def test_trace_summary_on_a_synthetic_trace(tmp_path):
+    name = ("void ta::map_vec_kernel<ta::F32, ta::FwdOp<7, false, false, "
+            "false, false>, 256, 1, false, true, 1>(ta::IoPtrs, long, long, long)")
+    grid = (1 << 28) // 4
+    rows, t = [], 0
+    warm, steps = bench.HEADLINE_WARMUP, bench.HEADLINE_STEPS
+    for i in range(warm + steps + 10):
+        dur = 800_000 if i < warm else 700_000
+        rows.append({"Kernel_Name": name, "Grid_Size_X": grid,
+                     "Start_Timestamp": t, "End_Timestamp": t + dur})
+        t += dur + 1000
+    # a dispatch of the same kernel at another size is not counted
+    rows.append({"Kernel_Name": name, "Grid_Size_X": 1024,
+                 "Start_Timestamp": t, "End_Timestamp": t + 5})
+    _write_trace(str(tmp_path / "trace" / "run_kernel_trace.csv"), rows)
+    out = str(tmp_path / "summary.txt")
+    bench.summarize(["trace", str(tmp_path / "trace"), out, "cmd"])
+    text = open(out).read()
+    assert f"sincos_tan_f32: grid {grid} calls {warm + steps + 10}" in text
+    assert "sincos_tan_f32_headline_timed: dispatches" in text
+    assert "average_ns 700000" in text
+    assert f"source_sha: {bench.source_hash()}" in text
