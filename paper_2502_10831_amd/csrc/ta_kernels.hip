@@ -5,8 +5,8 @@
 // global loads and stores (4 FP32 or 2 FP64 elements per access; 8-byte
 // accesses of 4 elements for 16-bit storage), with a launch shape per kernel
 // category (see shape_for) and 64-bit indexing.  The
-// per-piece coefficients live in LDS (one 200-byte copy per workgroup),
-// never in HBM.
+// per-piece coefficients live in LDS (one copy of 176-360 bytes per
+// workgroup, by kernel family), never in HBM.
 #include <hip/hip_runtime.h>
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
