@@ -55,7 +55,8 @@ def half_precision_uniform(n: int, kind: str, seed: int | None = None):
 
 
 def log_magnitude(n: int = 1 << 26, seed: int | None = None) -> np.ndarray:
-    """|x| = 10^U[0, 6], random sign (the large-|x| reduction).  FP32."""
+    """|x| = 10^U[0, 6], random sign: large arguments for the reduction
+    (q up to ~6.4e5), all below the 2^29 bit-table threshold.  FP32."""
     rng = _rng(seed)
     mag = 10.0 ** rng.uniform(0.0, 6.0, n)
     sign = np.where(rng.random(n) < 0.5, -1.0, 1.0)
