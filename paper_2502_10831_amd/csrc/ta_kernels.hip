@@ -129,6 +129,25 @@ struct F64 {
 // ---------------------------------------------------------------------------
 enum : int { kSin = 1, kCos = 2, kTan = 4 };
 
+// The output sign: from the quadrant masks for the FP64 folds (8-row
+// tables), already in N and D for the FP32 evaluation (the signed 32-row
+// FP16 table, FoldedL).
+template <class F, class V>
+__device__ inline V sgn_sin(const F &f, V v) {
+  if constexpr (std::is_same<F, FoldedL>::value) return v;
+  else return flip_sign(v, sin_mask(f));
+}
+template <class F, class V>
+__device__ inline V sgn_cos(const F &f, V v) {
+  if constexpr (std::is_same<F, FoldedL>::value) return v;
+  else return flip_sign(v, cos_mask(f));
+}
+template <class F, class V>
+__device__ inline V sgn_tan(const F &f, V v) {
+  if constexpr (std::is_same<F, FoldedL>::value) return v;
+  else return flip_sign(v, tan_mask(f));
+}
+
 // LOW: the variant for 16-bit storage.  Its outputs keep 8 (BF16) or 11
 // (FP16) significant bits, so the whole evaluation runs in FP32
 // (fold_forms_f32) and the hardware inverse square root and reciprocal (each
@@ -166,12 +185,11 @@ struct FwdOp {
     int o = 0;
     if constexpr ((MASK & (kSin | kCos)) != 0) {
       const float y = LOW ? rsqrt_est(v.q) : rsqrt_refined(v.q);
-      if constexpr (MASK & kSin) out[o++] = flip_sign(v.n * y, sin_mask(f));
-      if constexpr (MASK & kCos) out[o++] = flip_sign(v.d * y, cos_mask(f));
+      if constexpr (MASK & kSin) out[o++] = sgn_sin(f, v.n * y);
+      if constexpr (MASK & kCos) out[o++] = sgn_cos(f, v.d * y);
     }
     if constexpr (MASK & kTan) {
-      float t = flip_sign(LOW ? div_est(v.n, v.d) : div_refined(v.n, v.d),
-                          tan_mask(f));
+      float t = sgn_tan(f, LOW ? div_est(v.n, v.d) : div_refined(v.n, v.d));
       if constexpr (GUARD) {
         // Section 3 proposed_tan: +inf within 1e-3 of pi/2, before the sign.
         if ((f.q & 1u) && f.abs_r() < 1e-3) t = __builtin_inff();
@@ -187,11 +205,11 @@ struct FwdOp {
     int o = 0;
     if constexpr ((MASK & (kSin | kCos)) != 0) {
       const double y = rsqrt64_refined(v.q);
-      if constexpr (MASK & kSin) out[o++] = flip_sign(v.n * y, sin_mask(f));
-      if constexpr (MASK & kCos) out[o++] = flip_sign(v.d * y, cos_mask(f));
+      if constexpr (MASK & kSin) out[o++] = sgn_sin(f, v.n * y);
+      if constexpr (MASK & kCos) out[o++] = sgn_cos(f, v.d * y);
     }
     if constexpr (MASK & kTan) {
-      double t = flip_sign(div64_refined(v.n, v.d), tan_mask(f));
+      double t = sgn_tan(f, div64_refined(v.n, v.d));
       if constexpr (GUARD) {
         if ((f.q & 1u) && f.abs_r() < 1e-3) t = __builtin_inf();
       }
@@ -239,7 +257,7 @@ template <int WHICH, bool WITH_Y, bool LOW = false, bool SMALL = false>
 struct BwdOp {
   static constexpr int NIN = 2;  // x, gy
   static constexpr int NOUT = WITH_Y ? 2 : 1;
-  using Table = typename std::conditional<LOW, Tables16, TablesBwd>::type;
+  using Table = typename std::conditional<LOW, Tables16Bwd, TablesBwd>::type;
   using Low = BwdOp<WHICH, WITH_Y, true>;
   using LowH = BwdOp<WHICH, WITH_Y, true, true>;
   __device__ static void apply(const float *in, float *out, const Table &tb,
@@ -261,12 +279,12 @@ struct BwdOp {
       const float r = LOW ? rcp_est(v.d) : rcp_refined(v.d);
       const float dt = kdet * r * r;
       if constexpr (WITH_Y)
-        out[0] = flip_sign(LOW ? v.n * r : div_refined(v.n, v.d), tan_mask(f));
+        out[0] = sgn_tan(f, LOW ? v.n * r : div_refined(v.n, v.d));
       out[WITH_Y ? 1 : 0] = in[1] * dt;
     } else {
       const float y = LOW ? rsqrt_est(v.q) : rsqrt_refined(v.q);
-      const float s = flip_sign(v.n * y, sin_mask(f));
-      const float c = flip_sign(v.d * y, cos_mask(f));
+      const float s = sgn_sin(f, v.n * y);
+      const float c = sgn_cos(f, v.d * y);
       const float omega = kdet * y * y;
       if constexpr (WHICH == kSin) {
         if constexpr (WITH_Y) out[0] = s;
@@ -292,8 +310,8 @@ struct BwdOp {
       out[WITH_Y ? 1 : 0] = in[1] * dt;
     } else {
       const double y = rsqrt64_refined(v.q);
-      const double s = flip_sign(v.n * y, sin_mask(f));
-      const double c = flip_sign(v.d * y, cos_mask(f));
+      const double s = sgn_sin(f, v.n * y);
+      const double c = sgn_cos(f, v.d * y);
       const double omega = kdet * y * y;
       if constexpr (WHICH == kSin) {
         if constexpr (WITH_Y) out[0] = s;
@@ -311,7 +329,7 @@ template <bool HAS_GS, bool HAS_GC, bool LOW = false, bool SMALL = false>
 struct SinCosBwdOp {
   static constexpr int NIN = 1 + (HAS_GS ? 1 : 0) + (HAS_GC ? 1 : 0);
   static constexpr int NOUT = 1;
-  using Table = typename std::conditional<LOW, Tables16, TablesBwd>::type;
+  using Table = typename std::conditional<LOW, Tables16Bwd, TablesBwd>::type;
   using Low = SinCosBwdOp<HAS_GS, HAS_GC, true>;
   using LowH = SinCosBwdOp<HAS_GS, HAS_GC, true, true>;
   __device__ static void apply(const float *in, float *out, const Table &tb,
@@ -331,9 +349,9 @@ struct SinCosBwdOp {
     const float y = LOW ? rsqrt_est(v.q) : rsqrt_refined(v.q);
     const float omega = tb.kdet[f.row] * y * y;
     float acc = 0.0f;
-    if constexpr (HAS_GS) acc = in[1] * flip_sign(v.d * y, cos_mask(f));
+    if constexpr (HAS_GS) acc = in[1] * sgn_cos(f, v.d * y);
     if constexpr (HAS_GC)
-      acc = __builtin_fmaf(-in[HAS_GS ? 2 : 1], flip_sign(v.n * y, sin_mask(f)),
+      acc = __builtin_fmaf(-in[HAS_GS ? 2 : 1], sgn_sin(f, v.n * y),
                            acc);
     out[0] = omega * acc;
   }
@@ -344,9 +362,9 @@ struct SinCosBwdOp {
     const double y = rsqrt64_refined(v.q);
     const double omega = tb.kdet64[f.row] * y * y;
     double acc = 0.0;
-    if constexpr (HAS_GS) acc = in[1] * flip_sign(v.d * y, cos_mask(f));
+    if constexpr (HAS_GS) acc = in[1] * sgn_cos(f, v.d * y);
     if constexpr (HAS_GC)
-      acc = __builtin_fma(-in[HAS_GS ? 2 : 1], flip_sign(v.n * y, sin_mask(f)),
+      acc = __builtin_fma(-in[HAS_GS ? 2 : 1], sgn_sin(f, v.n * y),
                           acc);
     out[0] = omega * acc;
   }

@@ -88,14 +88,10 @@ __host__ __device__ constexpr double kdet_of_row(int idx) {
 // j + 4*(q & 1).  Stored as two arrays of 16-byte (intercept, slope) pairs,
 // for N and for D: the eight rows of one array then fill 32 distinct LDS
 // banks, so a wave reading rows of both quadrant families has no bank
-// conflict (rows of 32 bytes put rows j and j + 4 on the same banks).  The
-// FP32 copy for 16-bit storage is one 16-byte row per piece.
+// conflict (rows of 32 bytes put rows j and j + 4 on the same banks).
 // One lane writes it with immediates; the caller synchronises.
 struct Lin {
   double i, s;  // value = i + s t
-};
-struct alignas(16) LinF {  // one 16-byte LDS read per row
-  float iN, sN, iD, sD;
 };
 
 // Each kernel family writes only the arrays it reads: the forward (FP32 and
@@ -132,24 +128,98 @@ struct TablesBwd : TablesFwd {
     }
   }
 };
+// The table of the FP32 evaluation (16-bit storage, and FP32 storage under
+// the FP32-reduction flag) carries the output signs: 32 rows, row =
+// j | sr << 2 | q0 << 3 | q1 << 4 (j the 15-degree slot, q0 and q1 the low
+// bits of q, sr the sign of r), each holding base row b = j + 4 q0 with N
+// negated where sin x is negative, q1 ^ (sr & ~q0), and D negated where
+// cos x is negative, q1 ^ (q0 & ~sr).  sin = N y, cos = D y and tan = N / D
+// then come out signed (N = iN + sN t with both negated is exactly -N; Q is
+// unchanged) and these kernels apply no sign step.  The coefficients are
+// integers below 2048, exact in FP16: a row is four FP16 values, 8 bytes, so
+// the 32 rows span 256 bytes, one pass over the 64 LDS banks (no two rows
+// share a bank), and the FMA reads them as FP16 operands directly
+// (v_fma_mix_f32).  The byte offset of a row, 8 row, is one funnel shift
+// and one and-or: bits 5-7 of ((q : hr) >> 26) are sr, q0, q1.
+constexpr int kRows16 = 32;
+__host__ __device__ constexpr int row16_base(int row) {
+  return (row & 3) | ((row >> 1) & 4);
+}
+__host__ __device__ constexpr bool row_sin_neg(int row) {
+  return (((row >> 4) & 1) ^ (((row >> 2) & 1) & (((row >> 3) & 1) ^ 1))) != 0;
+}
+__host__ __device__ constexpr bool row_cos_neg(int row) {
+  return (((row >> 4) & 1) ^ (((row >> 3) & 1) & (((row >> 2) & 1) ^ 1))) != 0;
+}
+// 8 * row for slot j, quadrant bits q and the word whose bit 31 is the
+// sign of r.
+__device__ inline uint32_t row16_offset(uint32_t j, uint32_t q, uint32_t hr) {
+  return (__builtin_amdgcn_alignbit(q, hr, 26) & 0xe0u) | (j << 3);
+}
+struct alignas(8) CoefH {
+  _Float16 iN, sN, iD, sD;
+};
+// FP16 bit pattern of an integer |v| < 2048 (exact in FP16).
+__host__ __device__ constexpr uint32_t half_bits(int v) {
+  if (v == 0) return 0u;
+  const uint32_t sign = v < 0 ? 0x8000u : 0u;
+  const int a = v < 0 ? -v : v;
+  int e = 0;
+  while ((a >> (e + 1)) != 0) ++e;  // floor(log2 a), at most 10
+  return sign | (uint32_t(e + 15) << 10) | (uint32_t(a << (10 - e)) & 0x3ffu);
+}
+// Base row b as two words of FP16 pairs: (iN, sN) and (iD, sD), low half
+// first (the CoefH layout).
+__host__ __device__ constexpr uint32_t row_word(int b, int w) {
+  return w == 0 ? half_bits(int(piece_row(b).iN)) |
+                      (half_bits(int(piece_row(b).sN)) << 16)
+                : half_bits(int(piece_row(b).iD)) |
+                      (half_bits(int(piece_row(b).sD)) << 16);
+}
+// The forward table: lanes 0-31 write one row each, the base row's two words
+// picked among immediates by selects, the signs by flipping the FP16 sign
+// bits of both halves; the caller synchronises.
 struct Tables16 {
-  LinF f[8];
-  float kdet[8];
+  CoefH h[kRows16];
   // 1.5 2^23 for the rounding of x 2/pi, read once into a register: an FMA
   // with a register addend and a scalar factor is one instruction, where two
   // immediate operands cost a copy per element.
   float magic;
   static constexpr bool kUsed = true;
-  __device__ static void init(Tables16 &tb) {
-    if (threadIdx.x == 0) {
+  __device__ static void fill_row(Tables16 &tb, int i) {
+    const int b = row16_base(i);
+    uint32_t w0 = row_word(0, 0), w1 = row_word(0, 1);
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const PieceRow r = piece_row(i);
-        tb.f[i] = LinF{float(r.iN), float(r.sN), float(r.iD), float(r.sD)};
-        tb.kdet[i] = float(kdet_of_row(i));
+    for (int k = 1; k < 8; ++k)
+      if (b == k) {
+        w0 = row_word(k, 0);
+        w1 = row_word(k, 1);
       }
-      tb.magic = kRoundMagicF;
-    }
+    if (row_sin_neg(i)) w0 ^= 0x80008000u;
+    if (row_cos_neg(i)) w1 ^= 0x80008000u;
+    uint32_t *dst = reinterpret_cast<uint32_t *>(&tb.h[i]);
+    dst[0] = w0;
+    dst[1] = w1;
+    if (i == 0) tb.magic = kRoundMagicF;
+  }
+  __device__ static void init(Tables16 &tb) {
+    if (threadIdx.x < kRows16) fill_row(tb, int(threadIdx.x));
+  }
+};
+// The 16-bit backward adds (180/pi) det of each row's piece.
+struct Tables16Bwd : Tables16 {
+  float kdet[kRows16];
+  __device__ static void fill_row(Tables16Bwd &tb, int i) {
+    Tables16::fill_row(tb, i);
+    const int b = row16_base(i);
+    float kd = float(kdet_of_row(0));
+#pragma unroll
+    for (int k = 1; k < 8; ++k)
+      if (b == k) kd = float(kdet_of_row(k));
+    tb.kdet[i] = kd;
+  }
+  __device__ static void init(Tables16Bwd &tb) {
+    if (threadIdx.x < kRows16) fill_row(tb, int(threadIdx.x));
   }
 };
 
@@ -338,8 +408,9 @@ __device__ inline Forms forms(const Folded &f, const TablesFwd &tb) {
 // keeps the sign of a zero x.  The rounding of 2/pi can put q on the neighbour
 // of the nearest quadrant near odd multiples of pi/4, leaving |r| a little
 // above pi/4: slot 3 of the table continues both families, so that costs
-// nothing.  Larger BF16 values take the FP64 fold.  Then t = |r| 180/pi, N, D, Q by FP32 FMAs from the FP32
-// table row.  Relative errors (u = 2^-24): r 2u, t 4u, N and D 5u.
+// nothing.  Larger BF16 values take the FP64 fold.  Then t = |r| 180/pi,
+// and N, D (signed) and Q by FP32 FMAs from the signed FP16 row of
+// Tables16.  Relative errors (u = 2^-24): r 2u, t 4u, N and D 5u.
 // ---------------------------------------------------------------------------
 constexpr float kTwoOverPiF = 0x1.45f306p-1f;  // RN24(2/pi)
 constexpr float kPio2F1 = 0x1.921fb4p+0f;      // RD24(pi/2)
@@ -351,7 +422,8 @@ constexpr float kSmall16 = 0x1p16f;
 struct FoldedL {
   uint32_t q;    // quadrant, low bits
   uint32_t hr;   // bit 31 = sign of r
-  uint32_t row;  // table row j + 4*(q & 1)
+  uint32_t off;  // byte offset of the Tables16 row (8 row)
+  uint32_t row;  // the row, j | sr << 2 | q0 << 3 | q1 << 4
   float ar;      // |r|
   __device__ float abs_r() const { return ar; }
 };
@@ -373,18 +445,20 @@ __device__ inline Forms fold_forms_f32(float x, const Tables16 &tb, FoldedL &f) 
   f.hr = __float_as_uint(r);
   f.ar = __builtin_fabsf(r);
   float t = f.ar * kDegPerRadF;
-  f.row = ((f.q << 2) & 4u) | uint32_t(t * (1.0f / 15.0f));
+  f.off = row16_offset(uint32_t(t * (1.0f / 15.0f)), f.q, f.hr);
   if (MAY_BE_LARGE && __builtin_expect(!(__builtin_fabsf(x) < kSmall16), 0)) {
     const Folded g = fold(x);
     f.q = g.q;
     f.hr = g.hr;
-    f.row = g.row;
+    f.off = row16_offset(g.row & 3u, g.q, g.hr);  // slot j: low two bits
     f.ar = float(g.abs_r());
     t = float(g.t);
   }
-  const LinF c = tb.f[f.row];
-  const float n = __builtin_fmaf(c.sN, t, c.iN);
-  const float d = __builtin_fmaf(c.sD, t, c.iD);
+  f.row = f.off >> 3;
+  const CoefH c = *reinterpret_cast<const CoefH *>(
+      reinterpret_cast<const char *>(tb.h) + f.off);
+  const float n = __builtin_fmaf(float(c.sN), t, float(c.iN));  // signed N
+  const float d = __builtin_fmaf(float(c.sD), t, float(c.iD));  // signed D
   return Forms{n, d, __builtin_fmaf(n, n, d * d)};
 }
 
@@ -404,11 +478,14 @@ __device__ inline float rsqrt_refined(float q) {
 }
 
 // n/d: reciprocal estimate, quotient, exact residual n - d*t0, correction.
+// The residual is formed as d t0 - n and subtracted (the same value as
+// adding n - d t0), so that n = -0 (a signed table row) gives -0: +0 + -0
+// would round to +0.
 __device__ inline float div_refined(float n, float d) {
   const float r = __builtin_amdgcn_rcpf(d);
   const float t0 = n * r;
-  const float res = __builtin_fmaf(-d, t0, n);
-  return __builtin_fmaf(res, r, t0);
+  const float res = __builtin_fmaf(d, t0, -n);
+  return __builtin_fmaf(-res, r, t0);
 }
 
 // 1/d refined by one Newton step.
