@@ -503,8 +503,9 @@ struct IoPtrs {
 //   two FP32/FP64 inputs, one output (backward): 128 threads, two accesses,
 //     nontemporal loads and stores; two outputs (fused forward+backward):
 //     one access;
-//   16-bit storage (instruction-bound): four 8-byte accesses per thread,
-//     nontemporal loads and stores, 256 threads (128 with two inputs).
+//   16-bit storage (instruction-bound): 128 threads, four 8-byte accesses
+//     per thread, nontemporal loads and stores (3-4 % above 256 threads for
+//     several outputs, equal for one).
 // The TA_SHAPE_* macros exist only to re-time alternatives at build time.
 struct Shape {
   int block, unroll;
@@ -530,10 +531,7 @@ struct Shape {
 #define TA_SHAPE_TWOIN1 {128, 2, true, true}
 #endif
 #ifndef TA_SHAPE_HALF
-#define TA_SHAPE_HALF {256, 4, true, true}
-#endif
-#ifndef TA_SHAPE_HALF_TWOIN
-#define TA_SHAPE_HALF_TWOIN {128, 4, true, true}
+#define TA_SHAPE_HALF {128, 4, true, true}
 #endif
 // The copy comparators (the HBM ceiling a kernel is compared with): one
 // wave per workgroup, the fastest plain copy of 1 -> 3 and 2 -> 2 FP32
@@ -558,7 +556,7 @@ constexpr Shape shape_for() {
   if (sizeof(typename ST::raw) >= 4 && is_copy<Op>::value)
     return Shape TA_SHAPE_COPY;
   if (sizeof(typename ST::raw) == 2)
-    return Op::NIN >= 2 ? Shape TA_SHAPE_HALF_TWOIN : Shape TA_SHAPE_HALF;
+    return Shape TA_SHAPE_HALF;
   if (Op::NIN >= 2)
     return Op::NOUT == 1 ? Shape TA_SHAPE_TWOIN1 : Shape TA_SHAPE_TWOIN;
   if (Op::NOUT >= 2) return Shape TA_SHAPE_MULTI;
