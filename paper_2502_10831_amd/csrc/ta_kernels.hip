@@ -685,8 +685,9 @@ hipError_t launch(void (*kernel)(KArgs...), int64_t blocks, int threads,
 // writes; 2^j x is exact (it overflows to +-Inf, hence NaN, only for
 // |x| >= 2^(128-j) in FP32, 2^(1024-j) in FP64).  VEC_PATH: 16-byte accesses
 // (every plane then starts 16-byte aligned at element `head`), otherwise one
-// element per lane.
-constexpr int kEncodeBlock = 256;
+// element per lane.  128-thread groups with nontemporal stores: 12 % above
+// 256 threads (64, 192, 512 and plain stores were slower on MI355X).
+constexpr int kEncodeBlock = 128;
 __device__ inline float pow2(int j, float) {
   return __uint_as_float(uint32_t(127 + j) << 23);
 }
