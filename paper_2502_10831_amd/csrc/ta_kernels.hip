@@ -491,15 +491,17 @@ struct IoPtrs {
 
 // Launch shape of the vector body, per kernel category, chosen by timing on
 // MI355X (2^27-2^29 elements):
-//   one input, several FP32 or FP64 outputs: 256 threads, one 16-byte access
-//     per stream per thread, nontemporal stores;
+//   one input, several outputs: one 16-byte access per stream per thread,
+//     nontemporal stores; 256 threads for FP32 (7 % above 128), 128 for
+//     FP64 (3 % above 256);
 //   one FP32 output, the method (LDS table): two accesses per thread,
 //     nontemporal loads and stores, and at most 64 VGPRs (eight workgroups
 //     per CU: eight waves per SIMD; 5-6 % above four accesses in 86 VGPRs;
 //     the registers spilled are those of the rare large-argument branch);
 //     one FP64 output, the tan guard or the paper-literal arithmetic:
 //     four accesses;
-//   one FP32/FP64 output, light functors (Taylor, copy): one access;
+//   one FP32/FP64 output, light functors (Taylor, copy): one access, 128
+//     threads (2 % above 256);
 //   two FP32/FP64 inputs, one output (backward): 128 threads, two accesses,
 //     nontemporal loads and stores; two outputs (fused forward+backward):
 //     one access;
@@ -521,8 +523,11 @@ struct Shape {
 #ifndef TA_SHAPE_SINGLE_WIDE
 #define TA_SHAPE_SINGLE_WIDE {256, 4, true, true}
 #endif
+#ifndef TA_SHAPE_MULTI64
+#define TA_SHAPE_MULTI64 {128, 1, false, true}
+#endif
 #ifndef TA_SHAPE_LIGHT
-#define TA_SHAPE_LIGHT {256, 1, false, true}
+#define TA_SHAPE_LIGHT {128, 1, false, true}
 #endif
 #ifndef TA_SHAPE_TWOIN
 #define TA_SHAPE_TWOIN {128, 1, true, true}
@@ -559,7 +564,9 @@ constexpr Shape shape_for() {
     return Shape TA_SHAPE_HALF;
   if (Op::NIN >= 2)
     return Op::NOUT == 1 ? Shape TA_SHAPE_TWOIN1 : Shape TA_SHAPE_TWOIN;
-  if (Op::NOUT >= 2) return Shape TA_SHAPE_MULTI;
+  if (Op::NOUT >= 2)
+    return sizeof(typename ST::raw) == 8 ? Shape TA_SHAPE_MULTI64
+                                         : Shape TA_SHAPE_MULTI;
   // the functors that evaluate the method use the LDS table
   if (!Op::Table::kUsed) return Shape TA_SHAPE_LIGHT;
   // FP64 storage and the paper-literal FP64 arithmetic need more than 64
