@@ -739,6 +739,61 @@ def test_encode_f32(dev, n):
     assert np.array_equal(host(yc).view(np.uint32), yh[1].view(np.uint32))
 
 
+@pytest.mark.parametrize("kind,off", [("f32", 1), ("f32", 3), ("bf16", 1),
+                                      ("f16", 5)])
+def test_map_shared_misalignment(dev, kind, off):
+    """Inputs and outputs that all sit `off` elements past a 16-byte boundary
+    take a scalar head, then the 16-byte body, then a scalar tail; every
+    element equals that of the same call on 16-byte aligned buffers (whose
+    parity with the oracle the other tests check)."""
+    tdt = {"f32": torch.float32, "bf16": torch.bfloat16,
+           "f16": torch.float16}[kind]
+    n = (1 << 16) + 37
+    gen = torch.Generator().manual_seed(123)
+    x = (torch.rand(n, generator=gen, dtype=torch.float64) * 20 - 10).to(tdt)
+    g = torch.randn(n, generator=gen).to(tdt)
+    say(f"shared misalignment {kind} off={off} n={n}")
+
+    def at_offset(t):
+        buf = torch.empty(n + off, dtype=tdt, device=dev)
+        assert buf.data_ptr() % 16 == 0
+        buf[off:].copy_(t)
+        return buf[off:]
+
+    results = []
+    for xs, gs in ((x.to(dev), g.to(dev)), (at_offset(x), at_offset(g))):
+        o = [at_offset(torch.zeros(n, dtype=tdt)) if xs.data_ptr() % 16
+             else torch.zeros(n, dtype=tdt, device=dev) for _ in range(7)]
+        ta.ta_sin(xs, o[0])
+        ta.ta_sincos(xs, o[1], o[2], o[3])
+        ta.ta_sin_bwd(xs, gs, o[4])
+        ta.ta_sin_fwdbwd(xs, gs, o[5], o[6])
+        results.append([host(t.view(torch.int16) if t.element_size() == 2
+                             else t) for t in o])
+    for k, (u, v) in enumerate(zip(*results)):
+        assert u.tobytes() == v.tobytes(), (kind, off, k)
+
+
+def test_encode_f32_shared_misalignment(dev):
+    """x and y both 4 bytes past a 16-byte boundary: the 16-byte body starts
+    at element 3 of every plane, with a scalar head of 3 and tail of 1."""
+    n, nfreq = (1 << 18) + 8, 8
+    x = wl.small_uniform(n, seed=122)
+    xbuf = torch.empty(n + 1, device=dev)
+    ybuf = torch.empty(2 * nfreq * n + 1, device=dev)
+    assert xbuf.data_ptr() % 16 == 0 and ybuf.data_ptr() % 16 == 0
+    xd, y = xbuf[1:], ybuf[1:]
+    xd.copy_(torch.from_numpy(x))
+    say(f"encode shared misalignment n={n} nfreq={nfreq}")
+    ta.ta_sincos_encode(xd, y, nfreq)
+    yh = host(y).reshape(2 * nfreq, n)
+    for j in range(nfreq):
+        xj = x.astype(np.float64) * 2.0 ** j
+        ref = oracle.forward(xj)
+        check_f32(f"encm{j}:sin", xj, yh[2 * j], ref["sin"])
+        check_f32(f"encm{j}:cos", xj, yh[2 * j + 1], ref["cos"])
+
+
 @pytest.mark.parametrize("kind", ["f16", "bf16"])
 def test_encode_16bit_exhaustive(dev, kind):
     tdt = torch.float16 if kind == "f16" else torch.bfloat16
