@@ -54,8 +54,8 @@ struct F32 {
 // 16-bit formats round pairs: a <2 x float> -> <2 x half|bfloat>
 // conversion is one v_cvt_pk_{f16,bf16}_f32.  Accesses of TA_HALF_VEC
 // elements: 4 (8 bytes), so that four accesses per thread keep 16 elements
-// in flight in ~70 VGPRs (seven waves per SIMD); 8-element accesses need
-// ~128 VGPRs for the same work and ran 7-12 % slower.
+// in flight in 26-94 VGPRs; 8-element accesses need ~128 VGPRs for the same
+// work and ran 7-12 % slower.
 #ifndef TA_HALF_VEC
 #define TA_HALF_VEC 4
 #endif
