@@ -138,8 +138,8 @@ def main():
         summarize(args.summarize)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: the map has no cross-GPU step and "
-              "this build runs on a single MI355X (use --gpus 1).",
+        print("bench.py measures one GPU: the map has no cross-GPU step, "
+              "so runs on more than one GPU are not supported (use --gpus 1).",
               file=sys.stderr)
         sys.exit(2)
 
