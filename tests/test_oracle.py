@@ -347,6 +347,79 @@ def test_taylor_remainders_match_mpmath(golden_dir):
     assert abs(0.0 - t5["cos"][0]) >= tab[("cos", "taylor5_nosimd")][0] - 5e-7
 
 
+def _tangent_coefficients(count):
+    """c_j of tan(z) = sum_j c_j z^(2j+1), from the Bernoulli-number closed
+    form c_j = (-1)^j 2^(2n) (2^(2n) - 1) B_(2n) / (2n)!, n = j + 1, as exact
+    fractions (independent of the decimal or rational constants the oracle
+    carries)."""
+    from fractions import Fraction
+    out = []
+    for j in range(count):
+        n = j + 1
+        p, q = mpmath.bernfrac(2 * n)
+        b = Fraction(int(p), int(q))
+        c = (-1) ** j * 2 ** (2 * n) * (2 ** (2 * n) - 1) * b / \
+            math.factorial(2 * n)
+        out.append(c)
+    return out
+
+
+def test_taylor_tan_series_matches_bernoulli_form():
+    """Taylor-N tan is the first N terms of the tangent series (the Taylor
+    columns of Table 3).  Checked at rho = pi/2, 1.5 and 0.7 against the sum
+    built from the Bernoulli closed form of the coefficients, in 50-digit
+    arithmetic at the oracle's own folded angle: a change of one unit in any
+    numerator or denominator of the highest coefficients moves the sum by
+    more than 1e-8 relative at pi/2."""
+    mpmath.mp.dps = 50
+    coef = _tangent_coefficients(9)
+    # known first values of the series, as a check of the closed form itself
+    from fractions import Fraction
+    assert coef[:4] == [Fraction(1), Fraction(1, 3), Fraction(2, 15),
+                        Fraction(17, 315)]
+    for x in (math.pi / 2, 1.5, 0.7):
+        rho = float(oracle.fold([x])[0][0])
+        for terms in (5, 7, 9):
+            got = oracle.taylor([x], terms)["tan"][0]
+            want = sum(mpmath.mpf(c.numerator) / c.denominator *
+                       mpmath.mpf(rho) ** (2 * j + 1)
+                       for j, c in enumerate(coef[:terms]))
+            assert got == pytest.approx(float(want), rel=1e-13, abs=0), \
+                (x, terms)
+
+
+def test_forward_tan_guard_threshold():
+    """proposed_tan (Section 3) returns +infinity, before any sign, when the
+    folded angle is within 1e-3 of pi/2.  The oracle's guarded forward must
+    switch exactly there: +inf for v = 1e-3 - 1e-9 on either side of a pole
+    and for either sign of x, the piece's finite value for v = 1e-3 + 1e-9;
+    sin and cos do not depend on the flag."""
+    for m in (0, 1, 7, 300):
+        pole = (2 * m + 1) * math.pi / 2
+        for sgn in (1.0, -1.0):
+            for side in (1.0, -1.0):
+                inside = sgn * (pole + side * (1e-3 - 1e-9))
+                outside = sgn * (pole + side * (1e-3 + 1e-9))
+                g_in = oracle.forward([inside], flags=oracle.TAN_GUARD)
+                g_out = oracle.forward([outside], flags=oracle.TAN_GUARD)
+                p_in = oracle.forward([inside])
+                assert np.isposinf(g_in["tan"][0]), (m, sgn, side)
+                assert np.isfinite(g_out["tan"][0]), (m, sgn, side)
+                assert g_out["tan"][0] == oracle.forward([outside])["tan"][0]
+                assert np.isfinite(p_in["tan"][0])
+                assert abs(p_in["tan"][0]) > 900.0
+                for name in ("sin", "cos"):
+                    assert g_in[name][0] == p_in[name][0]
+    # the threshold is on the folded angle, not on x: far from any pole the
+    # flag changes nothing
+    x = np.linspace(-10, 10, 20001)
+    rho, v, _, _, _ = oracle.fold(x)
+    far = v > 1.001e-3
+    np.testing.assert_array_equal(
+        oracle.forward(x[far], flags=oracle.TAN_GUARD)["tan"],
+        oracle.forward(x[far])["tan"])
+
+
 def test_taylor_tan_reproduces_table3_worst_angle(golden_dir):
     """The Table 3 Taylor columns share one worst angle: abs/rel of the
     Taylor-5 (SIMD) column gives tan there; the Taylor-7 and -9 columns must

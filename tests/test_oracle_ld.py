@@ -167,3 +167,23 @@ def test_ld_gradient_matches_finite_differences():
     assert float(np.abs(om_t / om_s - 1).max()) < 64 * LD_EPS
     g64 = oracle.grad(x)
     assert float(np.abs(g64["sin"] - g["sin"]).max()) < 1e-14
+
+
+def test_ld_tan_guard_threshold():
+    """The guarded long-double tan switches to +infinity, unsigned, exactly
+    where proposed_tan's guard (Section 3) does: folded angle within 1e-3 of
+    pi/2 (v = 1e-3 - 1e-9 guarded, v = 1e-3 + 1e-9 not), for both signs of
+    x and both sides of a pole; sin and cos do not depend on the flag."""
+    for m in (0, 3, 300):
+        pole = (2 * m + 1) * math.pi / 2
+        for sgn in (1.0, -1.0):
+            for side in (1.0, -1.0):
+                x = [sgn * (pole + side * (1e-3 - 1e-9)),
+                     sgn * (pole + side * (1e-3 + 1e-9))]
+                g = oracle.forward_ld(x, flags=oracle.TAN_GUARD)
+                p = oracle.forward_ld(x)
+                assert np.isposinf(g["tan"][0]), (m, sgn, side)
+                assert np.isfinite(g["tan"][1]) and g["tan"][1] == p["tan"][1]
+                assert np.isfinite(p["tan"][0])
+                for name in ("sin", "cos"):
+                    np.testing.assert_array_equal(g[name], p[name])
