@@ -108,9 +108,9 @@ ta_status ta_cos(const void *x, void *y, int64_t n, ta_dtype dt,
  * TA_FLAG_FORCE_FP32_REDUCTION; TA_FLAG_TAN_GUARD is accepted and affects
  * tan outputs only). */
 ta_status ta_sin_ex(const void *x, void *y, int64_t n, ta_dtype dt,
-                    uint32_t flags, hipStream_t stream);
+                    hipStream_t stream, uint32_t flags);
 ta_status ta_cos_ex(const void *x, void *y, int64_t n, ta_dtype dt,
-                    uint32_t flags, hipStream_t stream);
+                    hipStream_t stream, uint32_t flags);
 /* y[i] = tan_a(x[i]).  Section 2, tangent cases; finite up to the
  * pole (the last piece's D vanishes only at exactly pi/2). */
 ta_status ta_tan(const void *x, void *y, int64_t n, ta_dtype dt,
@@ -122,9 +122,9 @@ ta_status ta_sincos(const void *x, void *ys, void *yc, void *yt, int64_t n,
 /* Same as above with flag bits (TA_FLAG_TAN_GUARD affects tan outputs;
  * TA_FLAG_FORCE_FP64_REDUCTION, TA_FLAG_FORCE_FP32_REDUCTION). */
 ta_status ta_tan_ex(const void *x, void *y, int64_t n, ta_dtype dt,
-                    uint32_t flags, hipStream_t stream);
+                    hipStream_t stream, uint32_t flags);
 ta_status ta_sincos_ex(const void *x, void *ys, void *yc, void *yt, int64_t n,
-                       ta_dtype dt, uint32_t flags, hipStream_t stream);
+                       ta_dtype dt, hipStream_t stream, uint32_t flags);
 
 /* ---- Taylor baseline (Section 3, Taylor comparison; Tables 1-3 columns) ----
  * The first `terms` (5, 7 or 9) non-zero Maclaurin terms of sin, cos or tan,
@@ -175,8 +175,8 @@ ta_status ta_tan_fwdbwd(const void *x, const void *gy, void *y, void *gx,
  * ta_sincos.  Any non-empty subset of ys/yc/yt; flags: TA_FLAG_TAN_GUARD,
  * TA_FLAG_LITERAL_DIVISOR, TA_FLAG_FORCE_FP64_REDUCTION. */
 ta_status ta_paper_sincos(const void *x, void *ys, void *yc, void *yt,
-                          int64_t n, ta_dtype dt, uint32_t flags,
-                          hipStream_t stream);
+                          int64_t n, ta_dtype dt, hipStream_t stream,
+                          uint32_t flags);
 
 /* ---- multi-frequency encoding (an application of the fused core) --------
  * For j = 0 .. nfreq-1 (1 <= nfreq <= 16), with y holding 2*nfreq planes of n

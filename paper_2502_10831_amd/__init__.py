@@ -73,11 +73,11 @@ def load(path: str | None = None):
         "ta_sin": [vp, vp, i64, i32, vp],
         "ta_cos": [vp, vp, i64, i32, vp],
         "ta_tan": [vp, vp, i64, i32, vp],
-        "ta_tan_ex": [vp, vp, i64, i32, u32, vp],
-        "ta_sin_ex": [vp, vp, i64, i32, u32, vp],
-        "ta_cos_ex": [vp, vp, i64, i32, u32, vp],
+        "ta_tan_ex": [vp, vp, i64, i32, vp, u32],
+        "ta_sin_ex": [vp, vp, i64, i32, vp, u32],
+        "ta_cos_ex": [vp, vp, i64, i32, vp, u32],
         "ta_sincos": [vp, vp, vp, vp, i64, i32, vp],
-        "ta_sincos_ex": [vp, vp, vp, vp, i64, i32, u32, vp],
+        "ta_sincos_ex": [vp, vp, vp, vp, i64, i32, vp, u32],
         "ta_taylor_sin": [vp, vp, i64, i32, i32, vp],
         "ta_taylor_cos": [vp, vp, i64, i32, i32, vp],
         "ta_taylor_tan": [vp, vp, i64, i32, i32, vp],
@@ -88,7 +88,7 @@ def load(path: str | None = None):
         "ta_sin_fwdbwd": [vp, vp, vp, vp, i64, i32, vp],
         "ta_cos_fwdbwd": [vp, vp, vp, vp, i64, i32, vp],
         "ta_tan_fwdbwd": [vp, vp, vp, vp, i64, i32, vp],
-        "ta_paper_sincos": [vp, vp, vp, vp, i64, i32, u32, vp],
+        "ta_paper_sincos": [vp, vp, vp, vp, i64, i32, vp, u32],
         "ta_sincos_encode": [vp, vp, i64, i32, i32, vp],
         "ta_builtin_sincos": [vp, vp, vp, vp, i64, i32, i32, vp],
         "ta_copy": [ctypes.POINTER(vp), i32, ctypes.POINTER(vp), i32, i64,
@@ -181,19 +181,19 @@ def ta_tan(x, y):
 def ta_sin_ex(x, y, flags: int):
     _dev(x, "x"); _same(x, ("y", y))
     n, dt, s = _args(x)
-    _check(load().ta_sin_ex(_ptr(x), _ptr(y), n, dt, int(flags), s))
+    _check(load().ta_sin_ex(_ptr(x), _ptr(y), n, dt, s, int(flags)))
 
 
 def ta_cos_ex(x, y, flags: int):
     _dev(x, "x"); _same(x, ("y", y))
     n, dt, s = _args(x)
-    _check(load().ta_cos_ex(_ptr(x), _ptr(y), n, dt, int(flags), s))
+    _check(load().ta_cos_ex(_ptr(x), _ptr(y), n, dt, s, int(flags)))
 
 
 def ta_tan_ex(x, y, flags: int):
     _dev(x, "x"); _same(x, ("y", y))
     n, dt, s = _args(x)
-    _check(load().ta_tan_ex(_ptr(x), _ptr(y), n, dt, int(flags), s))
+    _check(load().ta_tan_ex(_ptr(x), _ptr(y), n, dt, s, int(flags)))
 
 
 def ta_sincos(x, ys, yc, yt=None):
@@ -206,7 +206,7 @@ def ta_sincos_ex(x, ys, yc, yt, flags: int):
     _dev(x, "x"); _same(x, ("ys", ys), ("yc", yc), ("yt", yt))
     n, dt, s = _args(x)
     _check(load().ta_sincos_ex(_ptr(x), _ptr(ys), _ptr(yc), _ptr(yt), n, dt,
-                               int(flags), s))
+                               s, int(flags)))
 
 
 def _taylor_entry(name):
@@ -265,7 +265,7 @@ def ta_paper_sincos(x, ys=None, yc=None, yt=None, flags: int = 0):
     _dev(x, "x"); _same(x, ("ys", ys), ("yc", yc), ("yt", yt))
     n, dt, s = _args(x)
     _check(load().ta_paper_sincos(_ptr(x), _ptr(ys), _ptr(yc), _ptr(yt), n,
-                                  dt, int(flags), s))
+                                  dt, s, int(flags)))
 
 
 def ta_sincos_encode(x, y, nfreq: int):

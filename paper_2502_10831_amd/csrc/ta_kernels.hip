@@ -52,18 +52,15 @@ struct F32 {
 };
 
 // 16-bit formats round pairs: a <2 x float> -> <2 x half|bfloat>
-// conversion is one v_cvt_pk_{f16,bf16}_f32.  Accesses of TA_HALF_VEC
-// elements: 4 (8 bytes), so that four accesses per thread keep 16 elements
-// in flight in 26-94 VGPRs; 8-element accesses need ~128 VGPRs for the same
-// work and ran 7-12 % slower.
-#ifndef TA_HALF_VEC
-#define TA_HALF_VEC 4
-#endif
+// conversion is one v_cvt_pk_{f16,bf16}_f32.  Accesses of 4 elements (8
+// bytes), so that four accesses per thread keep 16 elements in flight in
+// 26-94 VGPRs; 8-element accesses need ~128 VGPRs for the same work and ran
+// 7-12 % slower.
 template <class Derived>
 struct Half16 {
   using raw = uint16_t;
   using val = float;
-  static constexpr int kVec = TA_HALF_VEC;
+  static constexpr int kVec = 4;
   using vec = uint32_t __attribute__((ext_vector_type(kVec / 2)));
   static __device__ void unpack(const vec &w, val *v) {
     raw h[kVec];
@@ -508,42 +505,23 @@ struct IoPtrs {
 //   16-bit storage (instruction-bound): 128 threads, four 8-byte accesses
 //     per thread, nontemporal loads and stores (3-4 % above 256 threads for
 //     several outputs, equal for one).
-// The TA_SHAPE_* macros exist only to re-time alternatives at build time.
 struct Shape {
   int block, unroll;
   bool nt_load, nt_store;
   int min_blocks = 1;  // __launch_bounds__ minimum workgroups per CU
 };
-#ifndef TA_SHAPE_MULTI
-#define TA_SHAPE_MULTI {256, 1, false, true}
-#endif
-#ifndef TA_SHAPE_SINGLE
-#define TA_SHAPE_SINGLE {256, 2, true, true, 8}
-#endif
-#ifndef TA_SHAPE_SINGLE_WIDE
-#define TA_SHAPE_SINGLE_WIDE {256, 4, true, true}
-#endif
-#ifndef TA_SHAPE_MULTI64
-#define TA_SHAPE_MULTI64 {128, 1, false, true}
-#endif
-#ifndef TA_SHAPE_LIGHT
-#define TA_SHAPE_LIGHT {128, 1, false, true}
-#endif
-#ifndef TA_SHAPE_TWOIN
-#define TA_SHAPE_TWOIN {128, 1, true, true}
-#endif
-#ifndef TA_SHAPE_TWOIN1
-#define TA_SHAPE_TWOIN1 {128, 2, true, true}
-#endif
-#ifndef TA_SHAPE_HALF
-#define TA_SHAPE_HALF {128, 4, true, true}
-#endif
+constexpr Shape kShapeMulti{256, 1, false, true};
+constexpr Shape kShapeSingle{256, 2, true, true, 8};
+constexpr Shape kShapeSingleWide{256, 4, true, true};
+constexpr Shape kShapeMulti64{128, 1, false, true};
+constexpr Shape kShapeLight{128, 1, false, true};
+constexpr Shape kShapeTwoIn{128, 1, true, true};
+constexpr Shape kShapeTwoIn1{128, 2, true, true};
+constexpr Shape kShapeHalf{128, 4, true, true};
 // The copy comparators (the HBM ceiling a kernel is compared with): one
 // wave per workgroup, the fastest plain copy of 1 -> 3 and 2 -> 2 FP32
 // arrays measured on MI355X (about 2 % above 256 threads).
-#ifndef TA_SHAPE_COPY
-#define TA_SHAPE_COPY {64, 1, false, true}
-#endif
+constexpr Shape kShapeCopy{64, 1, false, true};
 
 template <class Op, class = void>
 struct is_copy : std::false_type {};
@@ -559,22 +537,22 @@ struct wide_single<Op, std::void_t<decltype(Op::kWideSingle)>>
 template <class ST, class Op>
 constexpr Shape shape_for() {
   if (sizeof(typename ST::raw) >= 4 && is_copy<Op>::value)
-    return Shape TA_SHAPE_COPY;
+    return kShapeCopy;
   if (sizeof(typename ST::raw) == 2)
-    return Shape TA_SHAPE_HALF;
+    return kShapeHalf;
   if (Op::NIN >= 2)
-    return Op::NOUT == 1 ? Shape TA_SHAPE_TWOIN1 : Shape TA_SHAPE_TWOIN;
+    return Op::NOUT == 1 ? kShapeTwoIn1 : kShapeTwoIn;
   if (Op::NOUT >= 2)
-    return sizeof(typename ST::raw) == 8 ? Shape TA_SHAPE_MULTI64
-                                         : Shape TA_SHAPE_MULTI;
+    return sizeof(typename ST::raw) == 8 ? kShapeMulti64
+                                         : kShapeMulti;
   // the functors that evaluate the method use the LDS table
-  if (!Op::Table::kUsed) return Shape TA_SHAPE_LIGHT;
+  if (!Op::Table::kUsed) return kShapeLight;
   // FP64 storage and the paper-literal FP64 arithmetic need more than 64
   // VGPRs: four accesses per thread, no occupancy bound
   if (sizeof(typename ST::raw) == 8 || wide_single<Op>::value ||
       std::is_same<typename Op::Table, PaperTables>::value)
-    return Shape TA_SHAPE_SINGLE_WIDE;
-  return Shape TA_SHAPE_SINGLE;
+    return kShapeSingleWide;
+  return kShapeSingle;
 }
 
 template <bool NT, class V = u32x4>
@@ -990,38 +968,38 @@ using namespace ta;
 extern "C" {
 
 ta_status ta_sin_ex(const void *x, void *y, int64_t n, ta_dtype dt,
-                    uint32_t flags, hipStream_t s) {
+                    hipStream_t s, uint32_t flags) {
   void *o[1] = {y};
   return fwd_ex<kSin, false>(x, o, n, dt, flags, s);
 }
 
 ta_status ta_sin(const void *x, void *y, int64_t n, ta_dtype dt, hipStream_t s) {
-  return ta_sin_ex(x, y, n, dt, 0u, s);
+  return ta_sin_ex(x, y, n, dt, s, 0u);
 }
 
 ta_status ta_cos_ex(const void *x, void *y, int64_t n, ta_dtype dt,
-                    uint32_t flags, hipStream_t s) {
+                    hipStream_t s, uint32_t flags) {
   void *o[1] = {y};
   return fwd_ex<kCos, false>(x, o, n, dt, flags, s);
 }
 
 ta_status ta_cos(const void *x, void *y, int64_t n, ta_dtype dt, hipStream_t s) {
-  return ta_cos_ex(x, y, n, dt, 0u, s);
+  return ta_cos_ex(x, y, n, dt, s, 0u);
 }
 
 ta_status ta_tan_ex(const void *x, void *y, int64_t n, ta_dtype dt,
-                    uint32_t flags, hipStream_t s) {
+                    hipStream_t s, uint32_t flags) {
   void *o[1] = {y};
   if (flags & TA_FLAG_TAN_GUARD) return fwd_ex<kTan, true>(x, o, n, dt, flags, s);
   return fwd_ex<kTan, false>(x, o, n, dt, flags, s);
 }
 
 ta_status ta_tan(const void *x, void *y, int64_t n, ta_dtype dt, hipStream_t s) {
-  return ta_tan_ex(x, y, n, dt, 0u, s);
+  return ta_tan_ex(x, y, n, dt, s, 0u);
 }
 
 ta_status ta_sincos_ex(const void *x, void *ys, void *yc, void *yt, int64_t n,
-                       ta_dtype dt, uint32_t flags, hipStream_t s) {
+                       ta_dtype dt, hipStream_t s, uint32_t flags) {
   if (yt) {
     void *o[3] = {ys, yc, yt};
     if (flags & TA_FLAG_TAN_GUARD)
@@ -1034,7 +1012,7 @@ ta_status ta_sincos_ex(const void *x, void *ys, void *yc, void *yt, int64_t n,
 
 ta_status ta_sincos(const void *x, void *ys, void *yc, void *yt, int64_t n,
                     ta_dtype dt, hipStream_t s) {
-  return ta_sincos_ex(x, ys, yc, yt, n, dt, 0u, s);
+  return ta_sincos_ex(x, ys, yc, yt, n, dt, s, 0u);
 }
 
 ta_status ta_taylor_sin(const void *x, void *y, int64_t n, int terms,
@@ -1135,8 +1113,8 @@ ta_status ta_copy(const void *const *in, int n_in, void *const *out, int n_out,
 }
 
 ta_status ta_paper_sincos(const void *x, void *ys, void *yc, void *yt,
-                          int64_t n, ta_dtype dt, uint32_t flags,
-                          hipStream_t s) {
+                          int64_t n, ta_dtype dt, hipStream_t s,
+                          uint32_t flags) {
   if (!dtype_ok(dt)) return TA_EDTYPE;
   if (flags & ~uint32_t(TA_FLAG_TAN_GUARD | TA_FLAG_LITERAL_DIVISOR |
                        TA_FLAG_FORCE_FP64_REDUCTION))

@@ -32,12 +32,12 @@ int main(void) {
   expect("tan null", ta_tan(NULL, b, 16, TA_F32, NULL), TA_EINVAL);
   expect("sin overlap", ta_sin(a, (char *)a + 4, 16, TA_F32, NULL), TA_EOVERLAP);
   expect("sin n=0", ta_sin(NULL, NULL, 0, TA_BF16, NULL), TA_OK);
-  expect("sin_ex flags", ta_sin_ex(a, b, 16, TA_F32, 16u, NULL), TA_EINVAL);
-  expect("cos_ex f64+fp32", ta_cos_ex(a, b, 16, TA_F64, 4u, NULL), TA_EINVAL);
-  expect("tan_ex both", ta_tan_ex(a, b, 16, TA_F32, 6u, NULL), TA_EINVAL);
+  expect("sin_ex flags", ta_sin_ex(a, b, 16, TA_F32, NULL, 16u), TA_EINVAL);
+  expect("cos_ex f64+fp32", ta_cos_ex(a, b, 16, TA_F64, NULL, 4u), TA_EINVAL);
+  expect("tan_ex both", ta_tan_ex(a, b, 16, TA_F32, NULL, 6u), TA_EINVAL);
   expect("sincos yc", ta_sincos(a, b, NULL, NULL, 16, TA_F32, NULL), TA_EINVAL);
   expect("sincos_ex overlap",
-         ta_sincos_ex(a, b, bc + 32, bc + 16, 16, TA_F32, 0u, NULL), TA_EOVERLAP);
+         ta_sincos_ex(a, b, bc + 32, bc + 16, 16, TA_F32, NULL, 0u), TA_EOVERLAP);
   expect("taylor terms", ta_taylor_sin(a, b, 16, 6, TA_F32, NULL), TA_EINVAL);
   expect("taylor dtype", ta_taylor_cos(a, b, 16, 5, bad, NULL), TA_EDTYPE);
   expect("taylor n=0", ta_taylor_tan(a, b, 0, 9, TA_F32, NULL), TA_OK);
@@ -52,9 +52,9 @@ int main(void) {
          ta_cos_fwdbwd(a, b, bc + 512, bc + 520, 16, TA_F32, NULL), TA_EOVERLAP);
   expect("fwdbwd dtype",
          ta_tan_fwdbwd(a, b, bc + 512, bc + 1024, 16, bad, NULL), TA_EDTYPE);
-  expect("paper flags", ta_paper_sincos(a, b, NULL, NULL, 16, TA_F32, 4u, NULL),
+  expect("paper flags", ta_paper_sincos(a, b, NULL, NULL, 16, TA_F32, NULL, 4u),
          TA_EINVAL);
-  expect("paper none", ta_paper_sincos(a, NULL, NULL, NULL, 16, TA_F32, 0u, NULL),
+  expect("paper none", ta_paper_sincos(a, NULL, NULL, NULL, 16, TA_F32, NULL, 0u),
          TA_EINVAL);
   expect("encode nfreq", ta_sincos_encode(a, b, 16, 17, TA_F32, NULL), TA_EINVAL);
   expect("encode overlap", ta_sincos_encode(a, (char *)a + 32, 16, 4, TA_F32, NULL),

@@ -59,28 +59,28 @@ def test_unary_validation(lib):
 
 
 def test_sincos_validation(lib):
-    f = _fn(lib, "ta_sincos_ex", vp, vp, vp, vp, i64, i32, u32, vp)
-    assert f(A, B, None, None, 16, F32, 0, None) == EINVAL    # yc required
+    f = _fn(lib, "ta_sincos_ex", vp, vp, vp, vp, i64, i32, vp, u32)
+    assert f(A, B, None, None, 16, F32, None, 0) == EINVAL    # yc required
     # FP32 reduction: not for FP64 storage, not with the FP64 flag
-    assert f(A, B, B + 128, None, 16, F64, 4, None) == EINVAL
-    assert f(A, B, B + 32, None, 16, F32, 6, None) == EINVAL
-    assert f(A, B, B + 32, None, 16, F32, 8, None) == EINVAL  # paper-only flag
-    assert f(A, B, B + 32, None, 16, F32, 16, None) == EINVAL  # unknown
-    assert f(A, B, B + 32, B + 16, 16, F32, 0, None) == EOVERLAP
-    assert f(A, B, B, None, 16, F32, 0, None) == EOVERLAP     # ys == yc
-    assert f(A, B, B + 64, B + 128, 16, 4, 0, None) == EDTYPE
+    assert f(A, B, B + 128, None, 16, F64, None, 4) == EINVAL
+    assert f(A, B, B + 32, None, 16, F32, None, 6) == EINVAL
+    assert f(A, B, B + 32, None, 16, F32, None, 8) == EINVAL  # paper-only flag
+    assert f(A, B, B + 32, None, 16, F32, None, 16) == EINVAL  # unknown
+    assert f(A, B, B + 32, B + 16, 16, F32, None, 0) == EOVERLAP
+    assert f(A, B, B, None, 16, F32, None, 0) == EOVERLAP     # ys == yc
+    assert f(A, B, B + 64, B + 128, 16, 4, None, 0) == EDTYPE
     # FP64 elements are 8 bytes: 16 of them end at +128
-    assert f(A, B, B + 64, None, 16, F64, 0, None) == EOVERLAP
-    assert f(A, B, B + 64, None, 0, F32, 0, None) == OK
+    assert f(A, B, B + 64, None, 16, F64, None, 0) == EOVERLAP
+    assert f(A, B, B + 64, None, 0, F32, None, 0) == OK
     for name in ("ta_sin_ex", "ta_cos_ex", "ta_tan_ex"):
-        g = _fn(lib, name, vp, vp, i64, i32, u32, vp)
-        assert g(A, B, 16, F64, 4, None) == EINVAL, name
-        assert g(A, B, 16, F32, 6, None) == EINVAL, name
-        assert g(A, B, 16, F32, 8, None) == EINVAL, name
-        assert g(A, B, 16, F32, 16, None) == EINVAL, name
-        assert g(A, B, 16, 7, 0, None) == EDTYPE, name
-        assert g(A, A + 4, 16, F32, 4, None) == EOVERLAP, name
-        assert g(None, None, 0, F32, 4, None) == OK, name
+        g = _fn(lib, name, vp, vp, i64, i32, vp, u32)
+        assert g(A, B, 16, F64, None, 4) == EINVAL, name
+        assert g(A, B, 16, F32, None, 6) == EINVAL, name
+        assert g(A, B, 16, F32, None, 8) == EINVAL, name
+        assert g(A, B, 16, F32, None, 16) == EINVAL, name
+        assert g(A, B, 16, 7, None, 0) == EDTYPE, name
+        assert g(A, A + 4, 16, F32, None, 4) == EOVERLAP, name
+        assert g(None, None, 0, F32, None, 4) == OK, name
 
 
 def test_taylor_validation(lib):
@@ -112,14 +112,14 @@ def test_backward_validation(lib):
 
 
 def test_paper_validation(lib):
-    f = _fn(lib, "ta_paper_sincos", vp, vp, vp, vp, i64, i32, u32, vp)
-    assert f(A, None, None, None, 16, F32, 0, None) == EINVAL   # no output
-    assert f(A, None, None, None, 0, F32, 0, None) == OK
-    assert f(A, B, None, None, 16, F32, 4, None) == EINVAL      # bad flag
-    assert f(A, B, None, None, 16, F32, 16, None) == EINVAL
-    assert f(A, B, None, None, 16, 5, 0, None) == EDTYPE
-    assert f(A, B, B + 8, None, 16, F32, 3, None) == EOVERLAP
-    assert f(None, B, None, None, 16, F32, 0, None) == EINVAL
+    f = _fn(lib, "ta_paper_sincos", vp, vp, vp, vp, i64, i32, vp, u32)
+    assert f(A, None, None, None, 16, F32, None, 0) == EINVAL   # no output
+    assert f(A, None, None, None, 0, F32, None, 0) == OK
+    assert f(A, B, None, None, 16, F32, None, 4) == EINVAL      # bad flag
+    assert f(A, B, None, None, 16, F32, None, 16) == EINVAL
+    assert f(A, B, None, None, 16, 5, None, 0) == EDTYPE
+    assert f(A, B, B + 8, None, 16, F32, None, 3) == EOVERLAP
+    assert f(None, B, None, None, 16, F32, None, 0) == EINVAL
 
 
 def test_encode_validation(lib):
