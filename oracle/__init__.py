@@ -54,7 +54,7 @@ def _load():
     lib.ta_or_map.restype = ctypes.c_int
     lib.ta_or_fold_map.argtypes = [D, i64, D, D, I32, I32, I32]
     lib.ta_or_taylor_map.argtypes = [D, i64, ctypes.c_int, D, D, D, D, D, D]
-    lib.ta_or_grad_map.argtypes = [D, i64, D, D, D]
+    lib.ta_or_grad_map.argtypes = [D, i64, ctypes.c_int, D, D, D]
     lib.ta_or_fisr_map.argtypes = [D, i64, ctypes.c_double, D, D, D]
     lib.ta_or_paper_map.argtypes = [D, i64, ctypes.c_double, ctypes.c_uint,
                                     D, D, D]
@@ -157,14 +157,16 @@ def taylor(x, terms: int):
     return out
 
 
-def grad(x):
-    """d/dx of the method's sin, cos and tan (derivative of the piece)."""
+def grad(x, shift: int = 0):
+    """d/dx of the method's sin, cos and tan (derivative of the piece);
+    shift evaluates piece k + shift (clamped) instead of the piece rho falls
+    in."""
     lib = _load()
     x = _x(x)
     n = x.size
     out = {k: np.empty(n) for k in ("sin", "cos", "tan")}
-    lib.ta_or_grad_map(_dp(x), n, _dp(out["sin"]), _dp(out["cos"]),
-                       _dp(out["tan"]))
+    lib.ta_or_grad_map(_dp(x), n, int(shift), _dp(out["sin"]),
+                       _dp(out["cos"]), _dp(out["tan"]))
     return out
 
 

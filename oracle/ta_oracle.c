@@ -269,8 +269,12 @@ void ta_or_taylor_map(const double *x, int64_t n, int terms, double *ys,
  * The fold rho = arcsin|sin x| has d rho/dx = sign(sin x) * sign(cos x), and
  * the outputs carry the signs of sin x, cos x and their product.  The value
  * returned is the derivative of the selected piece (one-sided at the
- * discontinuities at 15, 30, 60 and 75 degrees and at the kink at 45). */
-static void or_grad_eval(double x, double *gs, double *gc, double *gt) {
+ * discontinuities at 15, 30, 60 and 75 degrees and at the kink at 45).
+ * `shift` evaluates piece k + shift (clamped to 0..5) instead: next to a
+ * jump node either neighbouring piece is a correct result (the boundary
+ * tie-break reading), and its derivative is the neighbour's. */
+static void or_grad_eval(double x, int shift, double *gs, double *gc,
+                         double *gt) {
   if (isnan(x) || isinf(x)) {
     *gs = *gc = *gt = NAN;
     return;
@@ -278,7 +282,9 @@ static void or_grad_eval(double x, double *gs, double *gc, double *gt) {
   double rho, v;
   int ns, nc;
   ta_or_fold(x, &rho, &v, &ns, &nc);
-  int k = ta_or_segment(rho);
+  int k = ta_or_segment(rho) + shift;
+  if (k < 0) k = 0;
+  if (k > 5) k = 5;
   double n, d;
   ta_or_piece(k, rho, v, &n, &d);
   double K = or_k();
@@ -294,12 +300,12 @@ static void or_grad_eval(double x, double *gs, double *gc, double *gt) {
   *gt = sig_s * sig_c * dT * drho_dx;
 }
 
-void ta_or_grad_map(const double *x, int64_t n, double *gs, double *gc,
-                    double *gt) {
+void ta_or_grad_map(const double *x, int64_t n, int shift, double *gs,
+                    double *gc, double *gt) {
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; ++i) {
     double a, b, c;
-    or_grad_eval(x[i], &a, &b, &c);
+    or_grad_eval(x[i], shift, &a, &b, &c);
     if (gs) gs[i] = a;
     if (gc) gc[i] = b;
     if (gt) gt[i] = c;

@@ -24,8 +24,8 @@ void ta_or_fold_map(const double *x, int64_t n, double *rho, double *v,
 void ta_or_taylor_map(const double *x, int64_t n, int terms, double *ys,
                       double *yc, double *yt, double *abs_s, double *abs_c,
                       double *abs_t);
-void ta_or_grad_map(const double *x, int64_t n, double *gs, double *gc,
-                    double *gt);
+void ta_or_grad_map(const double *x, int64_t n, int shift, double *gs,
+                    double *gc, double *gt);
 void ta_or_fisr_map(const double *rho, int64_t n, double divisor, double *ys,
                     double *yc, double *yt);
 void ta_or_paper_map(const double *x, int64_t n, double divisor,
@@ -74,7 +74,9 @@ int main(void) {
   ta_or_fold_map(x, n, a, b, k, s1, s2);
   for (int terms = 5; terms <= 9; terms += 2)
     ta_or_taylor_map(x, n, terms, a, b, c, d, e, f);
-  ta_or_grad_map(x, n, a, b, c);
+  ta_or_grad_map(x, n, 0, a, b, c);
+  ta_or_grad_map(x, n, 1, a, b, c);
+  ta_or_grad_map(x, n, -1, a, b, c);
   for (int i = 0; i < n; ++i) d[i] = fabs(fmod(x[i], M_PI / 2));
   ta_or_fisr_map(d, n, M_PI / 12, a, b, c);
   ta_or_fisr_map(d, n, 0.261, a, b, c);

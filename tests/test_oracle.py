@@ -455,6 +455,32 @@ def test_gradient_matches_finite_differences():
         np.testing.assert_allclose(g[name], fd, rtol=1e-6, atol=1e-8)
 
 
+def test_gradient_shift_is_the_neighbouring_piece_derivative():
+    """grad(x, shift) differentiates piece k + shift (clamped to 0..5):
+    checked against central differences of that piece's values (piece_scs)
+    at the same fold angle, on first-quadrant x where d rho/dx = 1."""
+    rng = np.random.default_rng(RNG_SEED + 1)
+    x = rng.uniform(0.02, math.pi / 2 - 0.02, 2000)
+    h = 1e-6
+    k0 = np.array([oracle.segment(r) for r in x])
+    for shift in (-1, 1):
+        g = oracle.grad(x, shift=shift)
+        for i in range(0, x.size, 7):
+            k = min(5, max(0, k0[i] + shift))
+            sp = oracle.piece_scs(k, x[i] + h, math.pi / 2 - x[i] - h)
+            sm = oracle.piece_scs(k, x[i] - h, math.pi / 2 - x[i] + h)
+            for j, name in enumerate(("sin", "cos", "tan")):
+                fd = (sp[j] - sm[j]) / (2 * h)
+                assert g[name][i] == pytest.approx(fd, rel=1e-6, abs=1e-8), \
+                    (shift, x[i], name)
+    # shift 0 is the plain derivative; a shift past the ends clamps
+    np.testing.assert_array_equal(oracle.grad(x, shift=0)["sin"],
+                                  oracle.grad(x)["sin"])
+    low = x[k0 == 0]
+    np.testing.assert_array_equal(oracle.grad(low, shift=-1)["sin"],
+                                  oracle.grad(low)["sin"])
+
+
 def test_gradient_closed_forms_and_trig_distance(dense_rho):
     g = oracle.grad([0.0])
     assert g["sin"][0] == pytest.approx(11 * 180 / (632 * math.pi), rel=1e-14)
