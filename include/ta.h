@@ -82,13 +82,16 @@ enum {
    * the flag changes nothing there; it is accepted by every call that takes
    * flags.  16-bit storage always evaluates in FP32 (below). */
   TA_FLAG_FORCE_FP64_REDUCTION = 2u,
-  /* Forward *_ex calls: reduce and evaluate in FP32, the evaluation 16-bit
-   * storage always uses (three-word FP32 Cody-Waite for |x| < 2^16, the
-   * FP64 fold above; N, D, Q by FP32 FMAs), keeping the refined inverse
-   * square root and reciprocal for FP32 outputs.  FP32 results are then
-   * within 4.5 FP32 ulp of the formula (4.36 measured over every FP32
-   * below 2^16) instead of 3.5.  No effect for 16-bit storage; TA_EINVAL
-   * with TA_F64 or with TA_FLAG_FORCE_FP64_REDUCTION. */
+  /* Forward *_ex calls on FP32 storage: reduce and evaluate in FP32, FP64
+   * only for |x| >= 2^20 (and +-Inf, NaN).  Below 2^20: a three-word FP32
+   * Cody-Waite reduction whose rounding error is carried as a second word,
+   * the angle in degrees split into a high part on a 2^-12 grid (so that the
+   * slope times it plus the intercept is exact) and a low part, each linear
+   * form one exact FMA plus one rounding FMA, then the refined inverse
+   * square root and reciprocal.  FP32 results stay within 4 FP32 ulp of the
+   * formula (3.16 measured over every FP32 below 2^20, against 2.53 for the
+   * default FP64 forms).  No effect for 16-bit storage (always evaluated in
+   * FP32); TA_EINVAL with TA_F64 or with TA_FLAG_FORCE_FP64_REDUCTION. */
   TA_FLAG_FORCE_FP32_REDUCTION = 4u,
   /* ta_paper_sincos only: index the pieces by floor(rho / 0.261) as the
    * pseudocode of proposed_sin / proposed_tan does (clamped to the last
@@ -195,15 +198,45 @@ ta_status ta_sincos_encode(const void *x, void *y, int64_t n, int nfreq,
  *   kind 0: sinf / cosf / tanf (accurate device library)
  *   kind 1: __sinf / __cosf / __tanf (hardware approximations)
  *   kind 2: sincosf + tanf
- * ys, yc required; yt may be NULL.  F32 only (TA_EDTYPE otherwise). */
+ * Outputs: ys alone, ys and yc, or ys, yc and yt (any other choice of NULLs
+ * is TA_EINVAL).  FP32, and FP16/BF16 storage (the FP32 function of the
+ * widened input, rounded to nearest even); FP64: the device library's double
+ * functions, kinds 0 and 2 (kind 1 is TA_EDTYPE). */
 ta_status ta_builtin_sincos(const void *x, void *ys, void *yc, void *yt,
                             int64_t n, int kind, ta_dtype dt,
                             hipStream_t stream);
+/* The sine activation's fused forward and backward with the built-in
+ * functions: y = sin x, gx = gy cos x, by sincosf (kind 0) or __sinf and
+ * __cosf (kind 1); FP64 storage: sincos (kind 0 only).  Same conventions as
+ * ta_sin_fwdbwd. */
+ta_status ta_builtin_sin_fwdbwd(const void *x, const void *gy, void *y,
+                                void *gx, int64_t n, int kind, ta_dtype dt,
+                                hipStream_t stream);
 /* Plain streaming copy with the same access pattern as the kernels: reads
  * n_in input arrays (1..3) and writes n_out outputs (1..3), out[j][i] =
  * in[j % n_in][i].  The achievable HBM ceiling for that byte mix. */
 ta_status ta_copy(const void *const *in, int n_in, void *const *out,
                   int n_out, int64_t n, ta_dtype dt, hipStream_t stream);
+
+/* Bandwidth probes: plain 16-byte streams over FP32 arrays of n elements
+ * (n a multiple of 4; every buffer 16-byte aligned; otherwise TA_EINVAL),
+ * one access per stream per thread, to measure what HBM delivers for a
+ * byte mix.
+ *   kind 0: read x (n_out = 1: out[0] is a sink of 1024 words, written at
+ *           most a few times);
+ *   kind 1: write n_out (1..3) arrays, x unused;
+ *   kind 2: copy x into n_out (1..3) arrays.
+ * flags: TA_PROBE_NT_LOAD / TA_PROBE_NT_STORE (nontemporal accesses),
+ * TA_PROBE_BLOCK256 (256-thread workgroups; 64 otherwise).  Overlapping
+ * buffers are TA_EOVERLAP. */
+enum {
+  TA_PROBE_NT_LOAD = 1u,
+  TA_PROBE_NT_STORE = 2u,
+  TA_PROBE_BLOCK256 = 4u
+};
+ta_status ta_stream_probe(int kind, const void *x, void *const *out,
+                          int n_out, int64_t n, uint32_t flags,
+                          hipStream_t stream);
 
 /* ---- utilities ---------------------------------------------------------- */
 const char *ta_status_str(ta_status s);

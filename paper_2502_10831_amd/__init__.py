@@ -27,7 +27,9 @@ __all__ = [
     "ta_taylor_sin", "ta_taylor_cos", "ta_taylor_tan",
     "ta_sin_bwd", "ta_cos_bwd", "ta_tan_bwd", "ta_sincos_bwd",
     "ta_sin_fwdbwd", "ta_cos_fwdbwd", "ta_tan_fwdbwd",
-    "ta_paper_sincos", "ta_sincos_encode", "ta_builtin_sincos", "ta_copy",
+    "ta_paper_sincos", "ta_sincos_encode", "ta_builtin_sincos",
+    "ta_builtin_sin_fwdbwd", "ta_copy", "ta_stream_probe",
+    "TA_PROBE_NT_LOAD", "TA_PROBE_NT_STORE", "TA_PROBE_BLOCK256",
     "sin", "cos", "tan", "sincos", "taylor",
     "SinFn", "CosFn", "TanFn", "SinCosFn",
     "TA_FLAG_TAN_GUARD", "TA_FLAG_LITERAL_DIVISOR",
@@ -43,6 +45,7 @@ TA_FLAG_TAN_GUARD = 1
 TA_FLAG_FORCE_FP64_REDUCTION = 2
 TA_FLAG_FORCE_FP32_REDUCTION = 4
 TA_FLAG_LITERAL_DIVISOR = 8
+TA_PROBE_NT_LOAD, TA_PROBE_NT_STORE, TA_PROBE_BLOCK256 = 1, 2, 4
 _DTYPE_CODE = {torch.float32: TA_F32, torch.float16: TA_F16,
                torch.bfloat16: TA_BF16, torch.float64: TA_F64}
 
@@ -91,6 +94,8 @@ def load(path: str | None = None):
         "ta_paper_sincos": [vp, vp, vp, vp, i64, i32, vp, u32],
         "ta_sincos_encode": [vp, vp, i64, i32, i32, vp],
         "ta_builtin_sincos": [vp, vp, vp, vp, i64, i32, i32, vp],
+        "ta_builtin_sin_fwdbwd": [vp, vp, vp, vp, i64, i32, i32, vp],
+        "ta_stream_probe": [i32, vp, ctypes.POINTER(vp), i32, i64, u32, vp],
         "ta_copy": [ctypes.POINTER(vp), i32, ctypes.POINTER(vp), i32, i64,
                     i32, vp],
     }
@@ -279,13 +284,38 @@ def ta_sincos_encode(x, y, nfreq: int):
     _check(load().ta_sincos_encode(_ptr(x), _ptr(y), n, int(nfreq), dt, s))
 
 
-def ta_builtin_sincos(x, ys, yc, yt=None, kind: int = 0):
+def ta_builtin_sincos(x, ys, yc=None, yt=None, kind: int = 0):
     """Comparator: the GPU's built-in sinf/cosf/tanf (kind 0), __sinf/...
-    (kind 1) or sincosf (kind 2) in the same streaming skeleton."""
+    (kind 1) or sincosf (kind 2) in the same streaming skeleton; outputs ys,
+    ys + yc, or ys + yc + yt."""
     _dev(x, "x"); _same(x, ("ys", ys), ("yc", yc), ("yt", yt))
     n, dt, s = _args(x)
     _check(load().ta_builtin_sincos(_ptr(x), _ptr(ys), _ptr(yc), _ptr(yt), n,
                                     int(kind), dt, s))
+
+
+def ta_builtin_sin_fwdbwd(x, gy, y, gx, kind: int = 0):
+    """Comparator: y = sin x, gx = gy cos x with the built-in functions
+    (kind 0 sincosf, kind 1 __sinf/__cosf) in the fused skeleton."""
+    _dev(x, "x"); _same(x, ("gy", gy), ("y", y), ("gx", gx))
+    n, dt, s = _args(x)
+    _check(load().ta_builtin_sin_fwdbwd(_ptr(x), _ptr(gy), _ptr(y), _ptr(gx),
+                                        n, int(kind), dt, s))
+
+
+def ta_stream_probe(kind: int, x, outs, flags: int = 0):
+    """Bandwidth probe (kind 0 read x into a 1024-word sink outs[0], 1 write
+    outs, 2 copy x into outs) over FP32 arrays of x's size."""
+    _dev(x, "x")
+    if x.dtype != torch.float32:
+        raise TaError("ta_stream_probe streams FP32 arrays")
+    for i, t in enumerate(outs):
+        _dev(t, f"out{i}")
+    n = x.numel()
+    s = torch.cuda.current_stream(x.device).cuda_stream
+    pout = (ctypes.c_void_p * len(outs))(*[t.data_ptr() for t in outs])
+    _check(load().ta_stream_probe(int(kind), _ptr(x), pout, len(outs), n,
+                                  int(flags), s))
 
 
 def ta_copy(ins, outs):

@@ -153,7 +153,8 @@ __device__ inline V sgn_tan(const F &f, V v) {
 // LowH for FP16, whose finite values all lie below 2^16 (SMALL: no test for
 // the FP64 fold; +-Inf and NaN come out NaN through the FP32 fold too).
 // F32RED (forward, FP32 storage, TA_FLAG_FORCE_FP32_REDUCTION): the FP32
-// evaluation with the refined inverse square root and reciprocal.
+// evaluation with the reduction residual carried (fold_forms_f32, CARRY) and
+// the refined inverse square root and reciprocal.
 template <int MASK, bool GUARD, bool LOW = false, bool F32RED = false,
           bool SMALL = false>
 struct FwdOp {
@@ -170,7 +171,7 @@ struct FwdOp {
                                   uint32_t) {
     if constexpr (kFp32Fold) {
       FoldedL f;
-      const Forms v = fold_forms_f32<!SMALL>(in[0], tb, f);
+      const Forms v = fold_forms_f32<!SMALL, F32RED>(in[0], tb, f);
       finish(f, v, out);
     } else {
       const Folded f = fold(in[0], tb.magic);
@@ -417,11 +418,13 @@ struct PaperOp {
   }
 };
 
-// Comparators: the GPU's built-in functions in the same skeleton.
-template <int KIND, bool WITH_TAN>
+// Comparators: the GPU's built-in functions in the same skeleton.  NO
+// outputs: sin (1), sin and cos (2), sin, cos and tan (3).  16-bit storage
+// evaluates the FP32 function on the widened input and rounds the result.
+template <int KIND, int NO>
 struct BuiltinOp {
   static constexpr int NIN = 1;
-  static constexpr int NOUT = WITH_TAN ? 3 : 2;
+  static constexpr int NOUT = NO;
   using Table = NoTable;
   using Low = BuiltinOp;
   using LowH = BuiltinOp;
@@ -430,18 +433,22 @@ struct BuiltinOp {
     const float x = in[0];
     if constexpr (KIND == 0) {
       out[0] = sinf(x);
-      out[1] = cosf(x);
-      if constexpr (WITH_TAN) out[2] = tanf(x);
+      if constexpr (NO >= 2) out[1] = cosf(x);
+      if constexpr (NO >= 3) out[2] = tanf(x);
     } else if constexpr (KIND == 1) {
       out[0] = __sinf(x);
-      out[1] = __cosf(x);
-      if constexpr (WITH_TAN) out[2] = __tanf(x);
+      if constexpr (NO >= 2) out[1] = __cosf(x);
+      if constexpr (NO >= 3) out[2] = __tanf(x);
     } else {
-      float s, c;
-      sincosf(x, &s, &c);
-      out[0] = s;
-      out[1] = c;
-      if constexpr (WITH_TAN) out[2] = tanf(x);
+      if constexpr (NO >= 2) {
+        float s, c;
+        sincosf(x, &s, &c);
+        out[0] = s;
+        out[1] = c;
+      } else {
+        out[0] = sinf(x);
+      }
+      if constexpr (NO >= 3) out[2] = tanf(x);
     }
   }
   // FP64: the device library's sin/cos/tan (kind 0) or sincos + tan (kind
@@ -449,16 +456,47 @@ struct BuiltinOp {
   __device__ static void apply(const double *in, double *out, const Table &,
                                uint32_t) {
     const double x = in[0];
-    if constexpr (KIND == 2) {
+    if constexpr (KIND == 2 && NO >= 2) {
       double s, c;
       sincos(x, &s, &c);
       out[0] = s;
       out[1] = c;
     } else {
       out[0] = sin(x);
-      out[1] = cos(x);
+      if constexpr (NO >= 2) out[1] = cos(x);
     }
-    if constexpr (WITH_TAN) out[2] = tan(x);
+    if constexpr (NO >= 3) out[2] = tan(x);
+  }
+};
+
+// The fused forward+backward of the sine activation with the built-in
+// functions: y = sin x, gx = gy cos x, by sincosf (kind 0) or __sinf and
+// __cosf (kind 1); FP64: sincos.
+template <int KIND>
+struct BuiltinFwdBwdOp {
+  static constexpr int NIN = 2;
+  static constexpr int NOUT = 2;
+  using Table = NoTable;
+  using Low = BuiltinFwdBwdOp;
+  using LowH = BuiltinFwdBwdOp;
+  __device__ static void apply(const float *in, float *out, const Table &,
+                               uint32_t) {
+    float s, c;
+    if constexpr (KIND == 0) {
+      sincosf(in[0], &s, &c);
+    } else {
+      s = __sinf(in[0]);
+      c = __cosf(in[0]);
+    }
+    out[0] = s;
+    out[1] = in[1] * c;
+  }
+  __device__ static void apply(const double *in, double *out, const Table &,
+                               uint32_t) {
+    double s, c;
+    sincos(in[0], &s, &c);
+    out[0] = s;
+    out[1] = in[1] * c;
   }
 };
 
@@ -760,6 +798,61 @@ hipError_t launch_encode(const void *x, void *y, int64_t n, int nfreq,
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
     return launch(encode_kernel<ST, false>, blocks, kEncodeBlock, stream, xc,
                   yc, n, nfreq, int64_t(0), n);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Bandwidth probes (measurement comparators, not the method): plain 16-byte
+// streams with one access per stream per thread, the kernels' pattern, to
+// measure what HBM delivers for a byte mix.  The read probe folds each
+// vector to one word and stores it only when it equals `key` (a value the
+// caller picks; the store target is a 1024-word sink), so that the loads
+// stay live while the probe writes next to nothing.
+// ---------------------------------------------------------------------------
+template <int BLOCK, bool NTL>
+__global__ __launch_bounds__(BLOCK) void probe_read_kernel(const char *x,
+                                                           int64_t nvec,
+                                                           uint32_t key,
+                                                           uint32_t *sink) {
+  const int64_t v = int64_t(blockIdx.x) * BLOCK + threadIdx.x;
+  if (v < nvec) {
+    const u32x4 w = vload<NTL>(x, v);
+    const uint32_t acc = w[0] ^ w[1] ^ w[2] ^ w[3];
+    if (acc == key) sink[blockIdx.x & 1023u] = acc;
+  }
+}
+// Writes (NIN = 0) or copies (NIN = 1) into NOUT arrays.
+template <int BLOCK, int NIN, int NOUT, bool NTL, bool NTS>
+__global__ __launch_bounds__(BLOCK) void probe_stream_kernel(IoPtrs io,
+                                                             int64_t nvec) {
+  const int64_t v = int64_t(blockIdx.x) * BLOCK + threadIdx.x;
+  if (v < nvec) {
+    u32x4 w = {uint32_t(v), 0u, 0u, 0u};
+    if constexpr (NIN == 1) w = vload<NTL>(io.in[0], v);
+#pragma unroll
+    for (int k = 0; k < NOUT; ++k) vstore<NTS>(io.out[k], v, w);
+  }
+}
+
+template <int BLOCK, bool NTL, bool NTS>
+hipError_t launch_probe(int kind, const void *x, void *const *out, int n_out,
+                        int64_t nvec, hipStream_t s) {
+  const int64_t blocks = (nvec + BLOCK - 1) / BLOCK;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  if (kind == 0)
+    return launch(probe_read_kernel<BLOCK, NTL>, blocks, BLOCK, s,
+                  static_cast<const char *>(x), nvec, 0x9e3779b9u,
+                  static_cast<uint32_t *>(out[0]));
+  IoPtrs io{};
+  io.in[0] = static_cast<const char *>(x);
+  for (int k = 0; k < n_out; ++k) io.out[k] = static_cast<char *>(out[k]);
+  switch ((kind == 2 ? 4 : 0) + n_out) {
+    case 1: return launch(probe_stream_kernel<BLOCK, 0, 1, NTL, NTS>, blocks, BLOCK, s, io, nvec);
+    case 2: return launch(probe_stream_kernel<BLOCK, 0, 2, NTL, NTS>, blocks, BLOCK, s, io, nvec);
+    case 3: return launch(probe_stream_kernel<BLOCK, 0, 3, NTL, NTS>, blocks, BLOCK, s, io, nvec);
+    case 5: return launch(probe_stream_kernel<BLOCK, 1, 1, NTL, NTS>, blocks, BLOCK, s, io, nvec);
+    case 6: return launch(probe_stream_kernel<BLOCK, 1, 2, NTL, NTS>, blocks, BLOCK, s, io, nvec);
+    default: return launch(probe_stream_kernel<BLOCK, 1, 3, NTL, NTS>, blocks, BLOCK, s, io, nvec);
   }
 }
 
@@ -1077,21 +1170,34 @@ ta_status ta_builtin_sincos(const void *x, void *ys, void *yc, void *yt,
                             int64_t n, int kind, ta_dtype dt, hipStream_t s) {
   if (!dtype_ok(dt)) return TA_EDTYPE;
   if (kind < 0 || kind > 2) return TA_EINVAL;
-  if (dt != TA_F32 && !(dt == TA_F64 && kind != 1)) return TA_EDTYPE;
+  if (dt == TA_F64 && kind == 1) return TA_EDTYPE;
+  if (!ys || (yt && !yc)) return n == 0 ? TA_OK : TA_EINVAL;
   const void *in[1] = {x};
-  void *o3[3] = {ys, yc, yt};
-  if (yt) {
-    switch (kind) {
-      case 0: return run<BuiltinOp<0, true>>(in, o3, n, dt, s);
-      case 1: return run<BuiltinOp<1, true>>(in, o3, n, dt, s);
-      default: return run<BuiltinOp<2, true>>(in, o3, n, dt, s);
-    }
+  void *o[3] = {ys, yc, yt};
+  const int no = yt ? 3 : (yc ? 2 : 1);
+  switch (kind * 4 + no) {
+    case 0 * 4 + 1: return run<BuiltinOp<0, 1>>(in, o, n, dt, s);
+    case 0 * 4 + 2: return run<BuiltinOp<0, 2>>(in, o, n, dt, s);
+    case 0 * 4 + 3: return run<BuiltinOp<0, 3>>(in, o, n, dt, s);
+    case 1 * 4 + 1: return run<BuiltinOp<1, 1>>(in, o, n, dt, s);
+    case 1 * 4 + 2: return run<BuiltinOp<1, 2>>(in, o, n, dt, s);
+    case 1 * 4 + 3: return run<BuiltinOp<1, 3>>(in, o, n, dt, s);
+    case 2 * 4 + 1: return run<BuiltinOp<2, 1>>(in, o, n, dt, s);
+    case 2 * 4 + 2: return run<BuiltinOp<2, 2>>(in, o, n, dt, s);
+    default: return run<BuiltinOp<2, 3>>(in, o, n, dt, s);
   }
-  switch (kind) {
-    case 0: return run<BuiltinOp<0, false>>(in, o3, n, dt, s);
-    case 1: return run<BuiltinOp<1, false>>(in, o3, n, dt, s);
-    default: return run<BuiltinOp<2, false>>(in, o3, n, dt, s);
-  }
+}
+
+ta_status ta_builtin_sin_fwdbwd(const void *x, const void *gy, void *y,
+                                void *gx, int64_t n, int kind, ta_dtype dt,
+                                hipStream_t s) {
+  if (!dtype_ok(dt)) return TA_EDTYPE;
+  if (kind < 0 || kind > 1) return TA_EINVAL;
+  if (dt == TA_F64 && kind == 1) return TA_EDTYPE;
+  const void *in[2] = {x, gy};
+  void *o[2] = {y, gx};
+  if (kind == 0) return run<BuiltinFwdBwdOp<0>>(in, o, n, dt, s);
+  return run<BuiltinFwdBwdOp<1>>(in, o, n, dt, s);
 }
 
 ta_status ta_copy(const void *const *in, int n_in, void *const *out, int n_out,
@@ -1110,6 +1216,48 @@ ta_status ta_copy(const void *const *in, int n_in, void *const *out, int n_out,
     case 3 * 4 + 2: return run<CopyOp<3, 2>>(in, out, n, dt, s);
     default: return run<CopyOp<3, 3>>(in, out, n, dt, s);
   }
+}
+
+ta_status ta_stream_probe(int kind, const void *x, void *const *out,
+                          int n_out, int64_t n, uint32_t flags,
+                          hipStream_t s) {
+  if (kind < 0 || kind > 2 || n < 0) return TA_EINVAL;
+  if (flags & ~uint32_t(TA_PROBE_NT_LOAD | TA_PROBE_NT_STORE |
+                       TA_PROBE_BLOCK256))
+    return TA_EINVAL;
+  if (kind == 0 ? n_out != 1 : (n_out < 1 || n_out > 3)) return TA_EINVAL;
+  if (n == 0) return TA_OK;
+  if (!out) return TA_EINVAL;
+  if (n % 4 != 0 || (kind != 1 && (!x || (uintptr_t(x) & 15u))))
+    return TA_EINVAL;
+  for (int k = 0; k < n_out; ++k)
+    if (!out[k] || (uintptr_t(out[k]) & 15u)) return TA_EINVAL;
+  // the read probe's sink is 1024 words; the other outputs are n floats
+  const uintptr_t obytes = kind == 0 ? 4096u : uintptr_t(n) * 4u;
+  const uintptr_t ib = uintptr_t(x), ibytes = uintptr_t(n) * 4u;
+  for (int j = 0; j < n_out; ++j) {
+    const uintptr_t o = uintptr_t(out[j]);
+    if (kind != 1 && o < ib + ibytes && ib < o + obytes) return TA_EOVERLAP;
+    for (int k = 0; k < j; ++k) {
+      const uintptr_t p = uintptr_t(out[k]);
+      if (o < p + obytes && p < o + obytes) return TA_EOVERLAP;
+    }
+  }
+  const int64_t nvec = n / 4;
+  const bool ntl = flags & TA_PROBE_NT_LOAD, nts = flags & TA_PROBE_NT_STORE;
+  hipError_t e;
+  if (flags & TA_PROBE_BLOCK256) {
+    e = ntl ? (nts ? launch_probe<256, true, true>(kind, x, out, n_out, nvec, s)
+                   : launch_probe<256, true, false>(kind, x, out, n_out, nvec, s))
+            : (nts ? launch_probe<256, false, true>(kind, x, out, n_out, nvec, s)
+                   : launch_probe<256, false, false>(kind, x, out, n_out, nvec, s));
+  } else {
+    e = ntl ? (nts ? launch_probe<64, true, true>(kind, x, out, n_out, nvec, s)
+                   : launch_probe<64, true, false>(kind, x, out, n_out, nvec, s))
+            : (nts ? launch_probe<64, false, true>(kind, x, out, n_out, nvec, s)
+                   : launch_probe<64, false, false>(kind, x, out, n_out, nvec, s));
+  }
+  return finish(e);
 }
 
 ta_status ta_paper_sincos(const void *x, void *ys, void *yc, void *yt,

@@ -398,7 +398,8 @@ __device__ inline Forms forms(const Folded &f, const TablesFwd &tb) {
 
 // ---------------------------------------------------------------------------
 // The evaluation in FP32: always for 16-bit storage (outputs keep 8 or 11
-// bits), and for FP32 storage with TA_FLAG_FORCE_FP32_REDUCTION.
+// bits), and, with the reduction residual carried (CARRY, below), for FP32
+// storage with TA_FLAG_FORCE_FP32_REDUCTION.
 // For |x| < 2^16 (every FP16 value, BF16 below 65536): q = the integer
 // nearest x RN(2/pi), by one FMA adding 1.5 2^23 (q is then the low bits of
 // that sum, and the sum less 1.5 2^23 is +0 when q = 0), and a three-word
@@ -417,7 +418,16 @@ constexpr float kPio2F1 = 0x1.921fb4p+0f;      // RD24(pi/2)
 constexpr float kPio2F2 = 0x1.4442d0p-24f;     // RD24(pi/2 - F1)
 constexpr float kPio2F3 = 0x1.84698ap-48f;     // RN24(pi/2 - F1 - F2)
 constexpr float kDegPerRadF = 0x1.ca5dc2p+5f;  // RN24(180/pi)
+constexpr float kDegPerRadLoF = -0x1.670f82p-21f;  // RN24(180/pi - kDegPerRadF)
 constexpr float kSmall16 = 0x1p16f;
+// The carried FP32 evaluation (FP32 storage) holds below 2^20: q < 2^20
+// keeps x 2/pi + 1.5 2^23 an exact integer rounding, and q times the
+// truncation of the three-word pi/2 (below 2^-72) stays under 2^-52, against
+// |r| >= 4.19e-9 for every FP32 below 2^20 (x = 252.898209 comes closest).
+constexpr float kSmall32 = 0x1p20f;
+// 1.5 2^11: (t + kGridT) - kGridT rounds t in [0, 64) degrees to a multiple
+// of 2^-12, so that s t + i is exact in FP32 for the table's integers.
+constexpr float kGridT = 0x1.8p11f;
 
 struct FoldedL {
   uint32_t q;    // quadrant, low bits
@@ -428,37 +438,82 @@ struct FoldedL {
   __device__ float abs_r() const { return ar; }
 };
 
+// CARRY (FP32 storage, outputs of 24 bits): the reduction keeps its
+// rounding error, r = rh + rl, and the degrees t = |r| 180/pi are carried
+// as t + tl with t on a 2^-12 grid, so that each linear form is one exact
+// FMA (s t + i: a multiple of 2^-12 below 2^12) and one rounding FMA that
+// adds s tl.  Steps, for |x| < 2^20:
+//   r1 = x - q C1 exactly (x and q C1 are multiples of 2^-22 for |x| >= 2,
+//   of 2^-24 for q = +-1 below that, and |r1| < 1); q C2 = ph + pl exactly
+//   (one product, one FMA); rh = r1 - ph with its error e by the three-op
+//   sum (exact: r1 is a multiple of 2^-22 >= ulp(ph)); rl = e - pl - q C3.
+//   t = |rh| 180/pi to 24 bits, then to the grid; tl = the exact remainder
+//   of |rh| K_hi, plus |rh| K_lo + |rl| K_hi (K_hi + K_lo = 180/pi).
+// Relative errors: r and t below 2^-40, N and D one rounding each (0.5u),
+// Q 1u; the outputs stay within about 3.1 ulp of the formula (against
+// 2.5 for FP64 forms rounded once).  Lanes with |x| >= 2^20, +-Inf or NaN
+// take the FP64 fold (t + tl from the FP64 degrees).
 // MAY_BE_LARGE false: the caller's inputs are below 2^16 or not finite (FP16
 // storage); +-Inf and NaN then give NaN r, t and forms, and the row (the
 // conversion of NaN is 0, the family bit is one bit) stays in the table.
-template <bool MAY_BE_LARGE = true>
+template <bool MAY_BE_LARGE = true, bool CARRY = false>
 __device__ inline Forms fold_forms_f32(float x, const Tables16 &tb, FoldedL &f) {
-  // The FP32 fold on every lane; lanes with |x| >= 2^16, +-Inf or NaN then
-  // overwrite it with the FP64 fold (a rare branch with no else side, so a
-  // wave without such lanes only tests and skips it).
+  // The FP32 fold on every lane; lanes at or above the threshold, +-Inf or
+  // NaN then overwrite it with the FP64 fold (a rare branch with no else
+  // side, so a wave without such lanes only tests and skips it).
   const float qb = __builtin_fmaf(x, kTwoOverPiF, tb.magic);
   const float qf = qb - kRoundMagicF;
-  float r = __builtin_fmaf(-qf, kPio2F1, x);
-  r = __builtin_fmaf(-qf, kPio2F2, r);
-  r = __builtin_fmaf(-qf, kPio2F3, r);
   f.q = __float_as_uint(qb);  // 2^22 + q in the mantissa: low bits of q
-  f.hr = __float_as_uint(r);
-  f.ar = __builtin_fabsf(r);
-  float t = f.ar * kDegPerRadF;
-  f.off = row16_offset(uint32_t(t * (1.0f / 15.0f)), f.q, f.hr);
-  if (MAY_BE_LARGE && __builtin_expect(!(__builtin_fabsf(x) < kSmall16), 0)) {
+  float t, tl = 0.0f;
+  if constexpr (CARRY) {
+    const float r1 = __builtin_fmaf(-qf, kPio2F1, x);
+    const float ph = qf * kPio2F2;
+    const float pl = __builtin_fmaf(qf, kPio2F2, -ph);
+    const float rh = r1 - ph;
+    const float rl = __builtin_fmaf(-qf, kPio2F3, ((r1 - rh) - ph) - pl);
+    f.hr = __float_as_uint(rh);
+    f.ar = __builtin_fabsf(rh);
+    // rl with the sign that makes |r| = f.ar + arl
+    const float arl = __uint_as_float(__float_as_uint(rl) ^ (f.hr & 0x80000000u));
+    const float th = f.ar * kDegPerRadF;
+    f.off = row16_offset(uint32_t(th * (1.0f / 15.0f)), f.q, f.hr);
+    t = (th + kGridT) - kGridT;
+    tl = __builtin_fmaf(f.ar, kDegPerRadF, -t) +
+         __builtin_fmaf(f.ar, kDegPerRadLoF, arl * kDegPerRadF);
+  } else {
+    float r = __builtin_fmaf(-qf, kPio2F1, x);
+    r = __builtin_fmaf(-qf, kPio2F2, r);
+    r = __builtin_fmaf(-qf, kPio2F3, r);
+    f.hr = __float_as_uint(r);
+    f.ar = __builtin_fabsf(r);
+    t = f.ar * kDegPerRadF;
+    f.off = row16_offset(uint32_t(t * (1.0f / 15.0f)), f.q, f.hr);
+  }
+  constexpr float kSmall = CARRY ? kSmall32 : kSmall16;
+  if (MAY_BE_LARGE && __builtin_expect(!(__builtin_fabsf(x) < kSmall), 0)) {
     const Folded g = fold(x);
     f.q = g.q;
     f.hr = g.hr;
     f.off = row16_offset(g.row & 3u, g.q, g.hr);  // slot j: low two bits
     f.ar = float(g.abs_r());
-    t = float(g.t);
+    if constexpr (CARRY) {
+      t = (float(g.t) + kGridT) - kGridT;
+      tl = float(g.t - double(t));
+    } else {
+      t = float(g.t);
+    }
   }
   f.row = f.off >> 3;
   const CoefH c = *reinterpret_cast<const CoefH *>(
       reinterpret_cast<const char *>(tb.h) + f.off);
-  const float n = __builtin_fmaf(float(c.sN), t, float(c.iN));  // signed N
-  const float d = __builtin_fmaf(float(c.sD), t, float(c.iD));  // signed D
+  float n, d;  // signed N and D
+  if constexpr (CARRY) {
+    n = __builtin_fmaf(float(c.sN), tl, __builtin_fmaf(float(c.sN), t, float(c.iN)));
+    d = __builtin_fmaf(float(c.sD), tl, __builtin_fmaf(float(c.sD), t, float(c.iD)));
+  } else {
+    n = __builtin_fmaf(float(c.sN), t, float(c.iN));
+    d = __builtin_fmaf(float(c.sD), t, float(c.iD));
+  }
   return Forms{n, d, __builtin_fmaf(n, n, d * d)};
 }
 

@@ -51,6 +51,39 @@ def neighbour_values(x):
     return near, alt
 
 
+def neighbour_grads(x):
+    """For inputs near a jump node: the oracle's derivatives (sin, cos, tan)
+    of the piece across the nearest node; NaN elsewhere.  Returns (near,
+    alt) like neighbour_values."""
+    rho, _, _, _, _ = oracle.fold(x)
+    step = math.pi / 12
+    knode = np.rint(rho / step)
+    near = (np.abs(rho - knode * step) < BAND) & np.isin(knode, (1, 2, 4, 5))
+    alt = {name: np.full(len(x), np.nan) for name in ("sin", "cos", "tan")}
+    idx = np.nonzero(near)[0]
+    if idx.size:
+        below = rho[idx] < knode[idx] * step   # neighbour: the next piece
+        for shift, sel in ((1, below), (-1, ~below)):
+            j = idx[sel]
+            if j.size:
+                g = oracle.grad(np.asarray(x, np.float64)[j], shift=shift)
+                for name in alt:
+                    alt[name][j] = g[name]
+    return near, alt
+
+
+def grad_bad(gpu, ref, tol, near=None, alt=None, tol_alt=None):
+    """Mask of gradient elements outside `tol` of `ref` that are not, in the
+    jump-node band (`near`), within `tol_alt` of the neighbouring piece's
+    value `alt`."""
+    gpu = np.asarray(gpu, np.float64)
+    bad = ~(np.abs(gpu - ref) <= tol)
+    if near is not None and bad.any():
+        ok_alt = np.abs(gpu - alt) <= tol_alt
+        bad &= ~(near & ok_alt)
+    return bad
+
+
 def ulp_error(gpu, ref):
     gpu = np.asarray(gpu, np.float64)
     ref = np.asarray(ref, np.float64)

@@ -137,11 +137,45 @@ def test_encode_validation(lib):
 
 def test_comparator_validation(lib):
     f = _fn(lib, "ta_builtin_sincos", vp, vp, vp, vp, i64, i32, i32, vp)
-    assert f(A, B, B + 256, None, 16, 0, F16, None) == EDTYPE
+    assert f(A, B, B + 256, None, 16, 0, 7, None) == EDTYPE
     assert f(A, B, B + 256, None, 16, 3, F32, None) == EINVAL
-    # no FP64 hardware approximations: kind 1 is FP32 only
+    assert f(A, B, B + 256, None, 16, -1, F16, None) == EINVAL
+    # no FP64 hardware approximations: kind 1 is not available for FP64
     assert f(A, B, B + 256, None, 16, 1, F64, None) == EDTYPE
-    assert f(A, B, B + 256, None, 16, 0, BF16, None) == EDTYPE
+    # outputs: ys, ys + yc or ys + yc + yt
+    assert f(A, None, B, None, 16, 0, F32, None) == EINVAL
+    assert f(A, B, None, B + 512, 16, 0, BF16, None) == EINVAL
+    assert f(A, None, None, None, 0, 0, F32, None) == OK
+    assert f(A, B, None, None, -1, 0, F32, None) == EINVAL
+    assert f(A, A + 4, None, None, 16, 0, F32, None) == EOVERLAP
+    fb = _fn(lib, "ta_builtin_sin_fwdbwd", vp, vp, vp, vp, i64, i32, i32, vp)
+    assert fb(A, B, B + 256, B + 512, 16, 2, F32, None) == EINVAL
+    assert fb(A, B, B + 256, B + 512, 16, 1, F64, None) == EDTYPE
+    assert fb(A, B, B + 256, B + 512, 16, 0, 9, None) == EDTYPE
+    assert fb(A, None, B + 256, B + 512, 16, 0, F32, None) == EINVAL
+    assert fb(A, B, B + 256, B + 256, 16, 0, F32, None) == EOVERLAP
+    assert fb(A, B, B + 256, B + 512, 0, 0, F32, None) == OK
+
+
+def test_stream_probe_validation(lib):
+    f = _fn(lib, "ta_stream_probe", i32, vp, ctypes.POINTER(vp), i32, i64,
+            u32, vp)
+    outs = (vp * 3)(B, B + 0x10000, B + 0x20000)
+    assert f(3, A, outs, 1, 16, 0, None) == EINVAL          # unknown kind
+    assert f(0, A, outs, 2, 16, 0, None) == EINVAL          # read: one sink
+    assert f(1, A, outs, 0, 16, 0, None) == EINVAL
+    assert f(2, A, outs, 4, 16, 0, None) == EINVAL
+    assert f(2, A, outs, 1, 18, 0, None) == EINVAL          # n % 4
+    assert f(2, A + 4, outs, 1, 16, 0, None) == EINVAL      # alignment
+    assert f(1, None, outs, 3, 16, 8, None) == EINVAL       # unknown flag
+    assert f(2, A, outs, 1, -4, 0, None) == EINVAL
+    assert f(2, None, outs, 1, 16, 0, None) == EINVAL       # copy needs x
+    assert f(2, B + 16, outs, 1, 16, 0, None) == EOVERLAP
+    same = (vp * 2)(B, B + 32)
+    assert f(1, None, same, 2, 16, 0, None) == EOVERLAP
+    sink = (vp * 1)(A + 1024)
+    assert f(0, A, sink, 1, 1024, 0, None) == EOVERLAP      # sink in x
+    assert f(2, A, outs, 3, 0, 7, None) == OK
     c = _fn(lib, "ta_copy", ctypes.POINTER(vp), i32, ctypes.POINTER(vp), i32,
             i64, i32, vp)
     ins = (vp * 1)(A)

@@ -74,9 +74,40 @@ def test_fp32_reduction_constants(text):
     assert f1 > 0 and f2 > 0 and f3 > 0
     assert (f1 * 2 ** 23) == mpmath.floor(f1 * 2 ** 23)
     assert abs(pi / 2 - f1 - f2 - f3) < mpmath.mpf(2) ** -72
-    assert _const_f(text, "kDegPerRadF") == _round24(180 / pi)
+    k_hi = _const_f(text, "kDegPerRadF")
+    assert k_hi == _round24(180 / pi)
     assert _const_f(text, "kRoundMagicF") == 1.5 * 2 ** 23
     assert _const_f(text, "kSmall16") == 2 ** 16
+    # the carried evaluation (FP32 storage under the flag): the low word of
+    # 180/pi, the threshold and the 2^-12-degree grid constant
+    k_lo = _const_f(text, "kDegPerRadLoF")
+    assert k_lo < 0 and -k_lo == _round24(k_hi - 180 / pi)
+    assert abs(180 / pi - k_hi - k_lo) < mpmath.mpf(2) ** -44
+    assert _const_f(text, "kSmall32") == 2 ** 20
+    assert _const_f(text, "kGridT") == 1.5 * 2 ** 11
+
+
+def test_carried_reduction_exactness_conditions(text):
+    """The carried FP32 reduction relies on: the first word of pi/2 a
+    multiple of 2^-22 (so x - q C1 is exact for |x| < 2^20, where x is a
+    multiple of 2^-22 or q is 0 or +-1); q < 2^22 (the 1.5 2^23 rounding
+    gives the integer nearest x 2/pi); q times the truncation of the three
+    words below 2^-52; and (t + 1.5 2^11) - 1.5 2^11 a multiple of 2^-12 for
+    t in [0, 64), so that s t + i (|s| <= 13, |i| <= 1252 integers) needs at
+    most 24 bits."""
+    mpmath.mp.prec = 400
+    pi = mpmath.pi
+    f1 = _const_f(text, "kPio2F1")
+    f2 = _const_f(text, "kPio2F2")
+    f3 = _const_f(text, "kPio2F3")
+    assert f1 * 2 ** 22 == mpmath.floor(f1 * 2 ** 22)
+    q_max = int(mpmath.ceil(2 ** 20 * 2 / pi))
+    assert q_max < 2 ** 22
+    assert q_max * abs(pi / 2 - f1 - f2 - f3) < mpmath.mpf(2) ** -52
+    grid = _const_f(text, "kGridT")
+    # every sum in [grid, grid + 64) has ulp 2^-12
+    assert grid >= 2 ** 11 and grid + 64 < 2 ** 12
+    assert (13 * 64 + 1252) * 2 ** 12 < 2 ** 24
 
 
 def test_two_over_pi_bits(text):
