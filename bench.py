@@ -164,7 +164,8 @@ def main():
         ta.ta_sincos(x, ys, yc, yt)
 
     log("timing ta_sincos (sin+cos+tan)")
-    per, total, wall = time_launches(step, args.steps, args.warmup, torch)
+    per, total, wall = time_launches(step, args.steps, args.warmup, torch,
+                                     WARM_S)
     ms_per_step = total / args.steps
     kernel_ms = sum(per) / len(per)
     pq = sorted(per)
@@ -176,7 +177,7 @@ def main():
     # with the same access pattern, timed the same way
     log("timing copy 1 -> 3 (ceiling)")
     cper, _, _ = time_launches(lambda: ta.ta_copy([x], [ys, yc, yt]),
-                               args.steps, args.warmup, torch)
+                               args.steps, args.warmup, torch, WARM_S)
     copy_gbs = 16 * n / (sum(cper) / len(cper) * 1e-3) / 1e9
     step()
     torch.cuda.synchronize()
@@ -191,6 +192,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "warmup_s_min": WARM_S,
         "ms_per_step": round(ms_per_step, 5),
         "higher_is_better": True,
         "scaling": "weak",
@@ -231,18 +233,50 @@ def main():
     out["timing_note"] = {"host_wall_ms_per_step": round(host_wall_ms, 4)}
 
     if not args.no_extras:
-        out["cpu_baseline"] = cpu_baseline(x_host, args.cpu_seconds)
+        out["cpu_baseline"], out["error_vs_oracle"] = oracle_leg(
+            x_host, args.cpu_seconds, (ys, yc, yt), torch, ta, dev)
+        out["stream_ceiling"] = stream_ceiling(x, ys, yc, yt, n, args, torch,
+                                               ta, kernel_ms)
         out["comparators"] = comparators(x, x_host, n, args, torch, ta, np)
         out["extra"] = extras(args, torch, ta, dev)
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(x_host, seconds):
-    """The FP64 oracle (untuned) on the host cores, bounded sample of the
-    same workload, sin+cos+tan outputs."""
+def _ulp_of(ref, mant_bits, min_exp):
+    """ulp of |ref| in a binary format with `mant_bits` stored significand
+    bits and smallest normal exponent `min_exp`."""
+    import numpy as np
+    r = np.abs(np.asarray(ref, np.float64))
+    _, e = np.frexp(r)
+    e = np.where(r > 0, np.maximum(e - 1, min_exp), min_exp)
+    return np.ldexp(1.0, e - mant_bits)
+
+
+def _err_stats(got, ref, mant_bits, min_exp):
+    """Max |got - ref| and max of it in ulp of ref (finite refs only)."""
+    import numpy as np
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    ok = np.isfinite(ref) & np.isfinite(got)
+    d = np.abs(got[ok] - ref[ok])
+    u = d / _ulp_of(ref[ok], mant_bits, min_exp)
+    return {"max_abs": float(d.max()), "max_ulp": round(float(u.max()), 3)}
+
+
+def oracle_leg(x_host, seconds, outs, torch, ta, dev):
+    """The FP64 oracle on the host: (1) the CPU baseline, the untuned oracle
+    timed on the host cores over a bounded sample of the headline workload
+    (sin+cos+tan); (2) the error of the GPU outputs against the oracle per
+    storage dtype, outside any timed region: FP32 on that sample of the
+    headline and on 2^20 elements of the 2^26 log-magnitude workload (the
+    default evaluation and the carried FP32 one), every BF16 and FP16 input
+    of the 16-bit workload (ulp of the 16-bit format), and 2^16 elements of
+    the 2^27 FP64 workload against the long-double form of the oracle (FP64
+    ulp).  This is the only use of the oracle in the benchmark."""
     import numpy as np
 
     import oracle
+    from paper_2502_10831_amd import workloads as wl
 
     threads = min(os.cpu_count() or 1, 16)
     probe = x_host[: 1 << 18].astype(np.float64)
@@ -268,13 +302,100 @@ def cpu_baseline(x_host, seconds):
                     break
     except OSError:
         pass
-    return {"value": round(m / dt / 1e9, 5), "unit": "Gelem/s",
+    base = {"value": round(m / dt / 1e9, 5), "unit": "Gelem/s",
             "cores": int(r["threads"]), "kind": "oracle",
             "sample": f"first {m} elements of the 2^28 workload, "
                       f"sin+cos+tan, {dt:.1f} s wall, {cpu_s:.1f} s CPU",
             "one_core": {"value": round(m1 / dt1 / 1e9, 5),
                          "sample": f"first {m1} elements, {dt1:.1f} s"},
             "cpu_model": model, "host_cpus": os.cpu_count()}
+
+    log("error vs the oracle per dtype")
+    names = ("sin", "cos", "tan")
+    err = {}
+    k = min(m, 1 << 22)
+    got = [t[:k].cpu().numpy() for t in outs]
+    err["f32_headline"] = {
+        nm: _err_stats(g, r[nm][:k], 23, -126) for nm, g in zip(names, got)}
+    err["f32_headline"]["sample"] = f"first {k} elements of the 2^28 workload"
+    xl = wl.log_magnitude(1 << 20)
+    rl = oracle.forward(xl.astype(np.float64))
+    xld = torch.from_numpy(xl).to(dev)
+    for flag, key in ((0, "f32_log_magnitude"),
+                      (ta.TA_FLAG_FORCE_FP32_REDUCTION,
+                       "f32_log_magnitude_carried_fp32")):
+        a, b, c = (torch.empty_like(xld) for _ in range(3))
+        ta.ta_sincos_ex(xld, a, b, c, flag)
+        err[key] = {nm: _err_stats(t.cpu().numpy(), rl[nm], 23, -126)
+                    for nm, t in zip(names, (a, b, c))}
+        err[key]["sample"] = "2^20 elements, |x| = 10^U[0,6], random sign"
+    for tdt, key, mant, emin in ((torch.bfloat16, "bf16", 7, -126),
+                                 (torch.float16, "f16", 10, -14)):
+        pat = torch.arange(1 << 16, dtype=torch.int32, device=dev).to(
+            torch.int16).view(tdt)
+        pat = pat[torch.isfinite(pat) & (pat.float().abs() <= math.pi)]
+        a, b, c = (torch.empty_like(pat) for _ in range(3))
+        ta.ta_sincos(pat, a, b, c)
+        rp = oracle.forward(pat.double().cpu().numpy())
+        err[key] = {nm: _err_stats(t.double().cpu().numpy(), rp[nm], mant, emin)
+                    for nm, t in zip(names, (a, b, c))}
+        err[key]["sample"] = (f"every {key} input in [-pi, pi] "
+                              f"({pat.numel()} values); ulp of {key}")
+    x64 = wl.protocol_f64(1 << 16, seed=39)
+    xd = torch.from_numpy(x64).to(dev)
+    a, b, c = (torch.empty_like(xd) for _ in range(3))
+    ta.ta_sincos(xd, a, b, c)
+    r64 = oracle.forward_ld(x64)
+    err["f64"] = {nm: _err_stats(t.cpu().numpy(),
+                                 np.asarray(r64[nm], np.float64), 52, -1022)
+                  for nm, t in zip(names, (a, b, c))}
+    err["f64"]["sample"] = ("2^16 elements U[-1e6, 1e6]; reference: the "
+                            "oracle in long double")
+    return base, err
+
+
+def stream_ceiling(x, ys, yc, yt, n, args, torch, ta, kernel_ms):
+    """What plain streams reach on this GPU in the same run, each after the
+    same warm-up: reads alone, writes alone, and copies with the headline's
+    byte mix (1 read, 3 writes) in several launch shapes; the headline kernel
+    as a fraction of the best of those copies."""
+    res = {}
+    sink = torch.zeros(1024, device=x.device)
+    P = ta
+    cases = [
+        ("read_only", 4, lambda: P.ta_stream_probe(0, x, [sink], P.TA_PROBE_BLOCK256)),
+        ("read_only_nt", 4, lambda: P.ta_stream_probe(
+            0, x, [sink], P.TA_PROBE_BLOCK256 | P.TA_PROBE_NT_LOAD)),
+        ("write_only_3_arrays_nt", 12, lambda: P.ta_stream_probe(
+            1, x, [ys, yc, yt], P.TA_PROBE_BLOCK256 | P.TA_PROBE_NT_STORE)),
+        ("write_only_3_arrays", 12, lambda: P.ta_stream_probe(
+            1, x, [ys, yc, yt], P.TA_PROBE_BLOCK256)),
+        ("copy_1to1", 8, lambda: P.ta_copy([x], [ys])),
+        ("copy_1to3_64thr_nt_store", 16, lambda: P.ta_copy([x], [ys, yc, yt])),
+        ("copy_1to3_256thr_nt_store", 16, lambda: P.ta_stream_probe(
+            2, x, [ys, yc, yt], P.TA_PROBE_BLOCK256 | P.TA_PROBE_NT_STORE)),
+        ("copy_1to3_256thr_nt_load_store", 16, lambda: P.ta_stream_probe(
+            2, x, [ys, yc, yt], P.TA_PROBE_BLOCK256 | P.TA_PROBE_NT_STORE |
+            P.TA_PROBE_NT_LOAD)),
+        ("copy_1to3_64thr_plain", 16, lambda: P.ta_stream_probe(
+            2, x, [ys, yc, yt], 0)),
+        ("copy_1to3_256thr_plain", 16, lambda: P.ta_stream_probe(
+            2, x, [ys, yc, yt], P.TA_PROBE_BLOCK256)),
+    ]
+    steps = max(5, args.steps // 2)
+    for name, nbytes, fn in cases:
+        log(f"timing stream probe {name}")
+        per, total, _ = time_launches(fn, steps, 3, torch, WARM_S)
+        ms = total / steps
+        res[name + "_gbs"] = round(nbytes * n / (ms * 1e-3) / 1e9, 1)
+    best = max(v for k, v in res.items() if k.startswith("copy_1to3"))
+    kernel_gbs = 16 * n / (kernel_ms * 1e-3) / 1e9
+    res["best_copy_1to3_gbs"] = best
+    res["headline_kernel_gbs"] = round(kernel_gbs, 1)
+    res["headline_frac_of_best_copy_1to3"] = round(kernel_gbs / best, 4)
+    res["note"] = ("FP32 arrays of 2^28 elements, 16-byte accesses, one per "
+                   "stream per thread; GB/s from the bytes each probe moves")
+    return res
 
 
 def comparators(x, x_host, n, args, torch, ta, np):
@@ -368,7 +489,20 @@ def comparators(x, x_host, n, args, torch, ta, np):
     per, total, _ = time_launches(f4, args.steps, args.warmup, torch, WARM_S)
     ms = total / args.steps
     res["ta_sin"] = {"gelem_s": round(n / (ms * 1e-3) / 1e9, 2),
-                     "gbs": round(8 * n / (ms * 1e-3) / 1e9, 1)}
+                     "gbs": round(8 * n / (ms * 1e-3) / 1e9, 1),
+                     "error_vs_libm": errors({"sin": ys})}
+    # the single-output shape with the built-in functions
+    for kind, label in ((0, "builtin_sinf_single"),
+                        (1, "builtin___sinf_single")):
+        def fb(kind=kind):
+            ta.ta_builtin_sincos(x, ys, kind=kind)
+        log(f"timing {label}")
+        per, total, _ = time_launches(fb, args.steps, args.warmup, torch,
+                                      WARM_S)
+        ms = total / args.steps
+        res[label] = {"gelem_s": round(n / (ms * 1e-3) / 1e9, 2),
+                      "gbs": round(8 * n / (ms * 1e-3) / 1e9, 1),
+                      "error_vs_libm": errors({"sin": ys})}
 
     # the FP32 fold and forms (TA_FLAG_FORCE_FP32_REDUCTION), fused and sin
     fl = ta.TA_FLAG_FORCE_FP32_REDUCTION
@@ -449,9 +583,15 @@ def extras(args, torch, ta, dev):
     def copy22():
         ta.ta_copy([x, g], [y, gx])
 
+    def builtin_fb(kind):
+        return lambda: ta.ta_builtin_sin_fwdbwd(x, g, y, gx, kind)
+
     for label, fn, nbytes in (("fused_fwdbwd", fused, 16),
                               ("separate_fwd_then_bwd", separate, 20),
                               ("torch_sin_then_g_times_cos", torch_ref, 28),
+                              ("builtin_sincosf_fused_fwdbwd", builtin_fb(0), 16),
+                              ("builtin___sinf___cosf_fused_fwdbwd",
+                               builtin_fb(1), 16),
                               ("copy_2in_2out_ceiling", copy22, 16)):
         log(f"timing {label}")
         per, total, _ = time_launches(fn, max(5, args.steps // 2), 3, torch,
@@ -462,6 +602,23 @@ def extras(args, torch, ta, dev):
                       "gbs_algorithmic": round(nbytes * n / (ms * 1e-3) / 1e9, 1)}
     res["fused_fwdbwd"]["hbm_frac"] = round(
         res["fused_fwdbwd"]["gbs_algorithmic"] / HBM_PEAK_GBS, 4)
+    # each fused kernel's outputs against libm on the first 2^20 elements:
+    # y vs sin x, and gx vs g cos x (for the method, the piece's derivative
+    # differs from cos x by up to 2.3e-2: the approximation's own slope)
+    import numpy as np
+    k = 1 << 20
+    xs = x[:k].double().cpu().numpy()
+    gs = g[:k].double().cpu().numpy()
+    for label, fn in (("fused_fwdbwd", fused),
+                      ("builtin_sincosf_fused_fwdbwd", builtin_fb(0)),
+                      ("builtin___sinf___cosf_fused_fwdbwd", builtin_fb(1))):
+        fn()
+        torch.cuda.synchronize()
+        res[label]["error_vs_libm"] = {
+            "y_max_abs_vs_sin": float(np.abs(y[:k].double().cpu().numpy()
+                                             - np.sin(xs)).max()),
+            "gx_max_abs_vs_g_cos": float(np.abs(gx[:k].double().cpu().numpy()
+                                                - gs * np.cos(xs)).max())}
     res["workload"] = ("ta_sin_fwdbwd, [128, 8192, 512] FP32, x ~ N(0, 100), "
                        "g ~ N(0, 1)")
     del x, g, y, gx
@@ -601,6 +758,25 @@ def other_workloads(args, torch, ta, dev):
                            "gbs_algorithmic": round(8 * n / (ms3 * 1e-3) / 1e9, 1)},
             "sin": {"gelem_s": round(n / (ms1 * 1e-3) / 1e9, 1),
                     "gbs_algorithmic": round(4 * n / (ms1 * 1e-3) / 1e9, 1)}}
+        # the built-in functions in the same 16-bit skeleton (evaluated in
+        # FP32 on the widened input), with their errors over the inputs
+        pat = torch.arange(1 << 16, dtype=torch.int32, device=dev).to(
+            torch.int16).view(tdt)
+        pat = pat[torch.isfinite(pat) & (pat.float().abs() <= math.pi)]
+        p64 = pat.double().cpu().numpy()
+        for kind, label in ((0, "builtin_sinf_cosf_tanf"),
+                            (1, "builtin___sinf___cosf___tanf")):
+            mb3 = timed(lambda: ta.ta_builtin_sincos(x, a, b, c, kind))
+            mb1 = timed(lambda: ta.ta_builtin_sincos(x, a, None, None, kind))
+            ps, pc, pt = (torch.empty_like(pat) for _ in range(3))
+            ta.ta_builtin_sincos(pat, ps, pc, pt, kind)
+            entry[label] = {
+                "sincos_tan_gelem_s": round(n / (mb3 * 1e-3) / 1e9, 1),
+                "sin_gelem_s": round(n / (mb1 * 1e-3) / 1e9, 1),
+                "error_vs_libm_over_inputs": libm_errors(
+                    p64, {"sin": ps.double().cpu().numpy(),
+                          "cos": pc.double().cpu().numpy(),
+                          "tan": pt.double().cpu().numpy()})}
         for key, kind, ms in (("sincos_tan", "sincos_tan_bf16", ms3),
                               ("sin", "sin_bf16", ms1)):
             if tag == "bf16" and kind in valu:
@@ -802,12 +978,14 @@ def summarize(a):
                 "sin_fwdbwd_f32": 16 * 128 * 8192 * 512,
                 "sincos_tan_f64": 32 * (1 << 27)}
         recs = {}
+        order = []  # every dispatch: (start, is the headline shape, duration)
         for r in _csv_rows(directory, "kernel_trace.csv"):
             key = _which(r.get("Kernel_Name", ""))
-            if key in grids and int(r["Grid_Size_X"]) == grids[key]:
-                recs.setdefault(key, []).append(
-                    (int(r["Start_Timestamp"]),
-                     int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+            t0, t1 = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
+            hit = key in grids and int(r["Grid_Size_X"]) == grids[key]
+            if hit:
+                recs.setdefault(key, []).append((t0, t1 - t0))
+            order.append((t0, hit and key == "sincos_tan_f32", t1 - t0))
         lines = [f"# rocprofv3 kernel trace (kernel-trace --stats), dispatches "
                  f"of the headline shapes", f"# command: {cmd}",
                  f"source_sha: {source_hash()}"]
@@ -819,15 +997,24 @@ def summarize(a):
                          f"average_ns {avg_ns:.0f} median_ns {d[len(d) // 2]} "
                          f"min_ns {d[0]} max_ns {d[-1]}")
             lines.append(f"{key}_algorithmic_GBs: {algo[key] / avg_ns:.1f}")
-        # the headline's timed launches: the bench's first dispatches of the
-        # fused FP32 kernel are its untimed warm-up, then the timed steps
-        head = recs.get("sincos_tan_f32", [])
-        w, k = HEADLINE_WARMUP, HEADLINE_STEPS
-        if len(head) >= w + k:
-            t = [x for _, x in head[w:w + k]]
+        # the headline's timed launches: the bench's first run of
+        # back-to-back dispatches of the fused FP32 kernel is its untimed
+        # warm-up (a count plus a time) followed by the timed steps, so the
+        # timed ones are the last HEADLINE_STEPS of that run
+        order.sort()
+        run = []
+        for _, hit, d in order:
+            if hit:
+                run.append(d)
+            elif run:
+                break
+        k = HEADLINE_STEPS
+        if len(run) >= k:
+            t = run[-k:]
             avg_t = sum(t) / len(t)
-            lines.append(f"sincos_tan_f32_headline_timed: dispatches {w + 1}..{w + k} "
-                         f"of the run, average_ns {avg_t:.0f} "
+            lines.append(f"sincos_tan_f32_headline_timed: the last {k} of the "
+                         f"first {len(run)} back-to-back dispatches, "
+                         f"average_ns {avg_t:.0f} "
                          f"({algo['sincos_tan_f32'] / avg_t:.1f} GB/s)")
         _write(out, lines)
     elif mode == "pmc":
