@@ -2,9 +2,9 @@
 //
 // Every entry point is an elementwise map: NIN input streams, NOUT output
 // streams, one functor per element.  The streaming skeleton issues 16-byte
-// global loads and stores (4 FP32 or 2 FP64 elements per access; 8-byte
-// accesses of 4 elements for 16-bit storage), with a launch shape per kernel
-// category (see shape_for) and 64-bit indexing.  The
+// global loads and stores (4 FP32, 8 FP16/BF16 or 2 FP64 elements per
+// access), with a launch shape per kernel category (see shape_for) and
+// 64-bit indexing.  The
 // per-piece coefficients live in LDS (one copy of 176-360 bytes per
 // workgroup, by kernel family), never in HBM.
 #include <hip/hip_runtime.h>
@@ -52,16 +52,14 @@ struct F32 {
 };
 
 // 16-bit formats round pairs: a <2 x float> -> <2 x half|bfloat>
-// conversion is one v_cvt_pk_{f16,bf16}_f32.  Accesses of 4 elements (8
-// bytes), so that four accesses per thread keep 16 elements in flight in
-// 26-94 VGPRs; 8-element accesses need ~128 VGPRs for the same work and ran
-// 7-12 % slower.
+// conversion is one v_cvt_pk_{f16,bf16}_f32.  Accesses of 8 elements (16
+// bytes, 46-52 VGPRs with the FP32 evaluation).
 template <class Derived>
 struct Half16 {
   using raw = uint16_t;
   using val = float;
-  static constexpr int kVec = 4;
-  using vec = uint32_t __attribute__((ext_vector_type(kVec / 2)));
+  static constexpr int kVec = 8;
+  using vec = u32x4;
   static __device__ void unpack(const vec &w, val *v) {
     raw h[kVec];
     __builtin_memcpy(h, &w, sizeof(vec));
@@ -540,9 +538,11 @@ struct IoPtrs {
 //   two FP32/FP64 inputs, one output (backward): 128 threads, two accesses,
 //     nontemporal loads and stores; two outputs (fused forward+backward):
 //     one access;
-//   16-bit storage (instruction-bound): 128 threads, four 8-byte accesses
-//     per thread, nontemporal loads and stores (3-4 % above 256 threads for
-//     several outputs, equal for one).
+//   16-bit storage, nontemporal loads and stores: one input and one output,
+//     128 threads and two accesses per thread (BF16 sin 1625 Gelem/s against
+//     1495 with four 8-byte accesses); every other category 256 threads and
+//     one access (within 1-3 % of the best 8-byte shapes for several
+//     outputs, 2-5 % above them for the backward).
 struct Shape {
   int block, unroll;
   bool nt_load, nt_store;
@@ -555,7 +555,8 @@ constexpr Shape kShapeMulti64{128, 1, false, true};
 constexpr Shape kShapeLight{128, 1, false, true};
 constexpr Shape kShapeTwoIn{128, 1, true, true};
 constexpr Shape kShapeTwoIn1{128, 2, true, true};
-constexpr Shape kShapeHalf{128, 4, true, true};
+constexpr Shape kShapeHalfSingle{128, 2, true, true};
+constexpr Shape kShapeHalf{256, 1, true, true};
 // The copy comparators (the HBM ceiling a kernel is compared with): one
 // wave per workgroup, the fastest plain copy of 1 -> 3 and 2 -> 2 FP32
 // arrays measured on MI355X (about 2 % above 256 threads).
@@ -577,7 +578,7 @@ constexpr Shape shape_for() {
   if (sizeof(typename ST::raw) >= 4 && is_copy<Op>::value)
     return kShapeCopy;
   if (sizeof(typename ST::raw) == 2)
-    return kShapeHalf;
+    return Op::NIN == 1 && Op::NOUT == 1 ? kShapeHalfSingle : kShapeHalf;
   if (Op::NIN >= 2)
     return Op::NOUT == 1 ? kShapeTwoIn1 : kShapeTwoIn;
   if (Op::NOUT >= 2)
@@ -707,53 +708,89 @@ hipError_t launch(void (*kernel)(KArgs...), int64_t blocks, int threads,
 // cos_a(2^j x), j < nfreq, each plane n elements long.  One read of x, 2 nfreq
 // writes; 2^j x is exact (it overflows to +-Inf, hence NaN, only for
 // |x| >= 2^(128-j) in FP32, 2^(1024-j) in FP64).  VEC_PATH: 16-byte accesses
-// (every plane then starts 16-byte aligned at element `head`), otherwise one
-// element per lane.  128-thread groups with nontemporal stores: 12 % above
-// 256 threads (64, 192, 512 and plain stores were slower on MI355X).
+// (every plane then starts 16-byte aligned at element `head`), U of them per
+// thread, block-strided, so that per frequency a workgroup writes U * 2 KiB
+// contiguous to each plane and issues the U stores of one plane together;
+// otherwise one element per lane.  128-thread groups with nontemporal stores.
+// At 2^26 FP32 inputs and 8 frequencies, U = 4 moves 6.47 TB/s against 6.02
+// for U = 1 (0.94 of the same-run write-only fill); a launch bound of two or
+// four groups per CU made the compiler spill and fall to ~0.95 TB/s.
 constexpr int kEncodeBlock = 128;
+template <class ST>
+constexpr int encode_unroll() {
+  return sizeof(typename ST::raw) == 4 ? 4 : 1;
+}
 __device__ inline float pow2(int j, float) {
   return __uint_as_float(uint32_t(127 + j) << 23);
 }
 __device__ inline double pow2(int j, double) {
   return __longlong_as_double(int64_t(1023 + j) << 52);
 }
-template <class ST, bool VEC_PATH>
+template <class ST, bool VEC_PATH, int UNROLL>
 __global__ __launch_bounds__(kEncodeBlock) void encode_kernel(
     const char *x, char *y, int64_t n, int nfreq, int64_t head, int64_t nvec) {
   using raw = typename ST::raw;
   using val = typename ST::val;
   using Core = FwdOp<kSin | kCos, false, sizeof(raw) == 2>;
   constexpr int VEC = VEC_PATH ? ST::kVec : 1;
+  constexpr int U = VEC_PATH ? UNROLL : 1;
   __shared__ typename Core::Table tb;
   Core::Table::init(tb);
   __syncthreads();
   const int64_t plane = n * int64_t(sizeof(raw));
-  const int64_t v = int64_t(blockIdx.x) * kEncodeBlock + threadIdx.x;
-  if (v < nvec) {
-    val xf[VEC];
-    if constexpr (VEC_PATH) {
-      ST::unpack(vload<false, typename ST::vec>(x + head * int64_t(sizeof(raw)), v), xf);
-    } else {
-      xf[0] = ST::load(reinterpret_cast<const raw *>(x)[v]);
-    }
-    for (int j = 0; j < nfreq; ++j) {
-      val sv[VEC], cv[VEC];
+  const int64_t v0 = int64_t(blockIdx.x) * (U * kEncodeBlock) + threadIdx.x;
+  const char *xb = x + head * int64_t(sizeof(raw));
+  val xf[U][VEC];
 #pragma unroll
-      for (int e = 0; e < VEC; ++e) {
-        const val in[1] = {xf[e] * pow2(j, val())};
-        val out[2];
-        Core::apply(in, out, tb, 0u);
-        sv[e] = out[0];
-        cv[e] = out[1];
-      }
-      char *ps = y + (2 * j) * plane;
-      char *pc = ps + plane;
+  for (int u = 0; u < U; ++u) {
+    const int64_t v = v0 + int64_t(u) * kEncodeBlock;
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) xf[u][e] = val(0);
+    if (v < nvec) {
       if constexpr (VEC_PATH) {
-        vstore<true>(ps + head * int64_t(sizeof(raw)), v, ST::pack(sv));
-        vstore<true>(pc + head * int64_t(sizeof(raw)), v, ST::pack(cv));
+        ST::unpack(vload<false, typename ST::vec>(xb, v), xf[u]);
       } else {
-        reinterpret_cast<raw *>(ps)[v] = ST::store(sv[0]);
-        reinterpret_cast<raw *>(pc)[v] = ST::store(cv[0]);
+        xf[u][0] = ST::load(reinterpret_cast<const raw *>(x)[v]);
+      }
+    }
+  }
+  if (v0 < nvec) {
+    for (int j = 0; j < nfreq; ++j) {
+      val sv[U][VEC], cv[U][VEC];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+          const val in[1] = {xf[u][e] * pow2(j, val())};
+          val out[2];
+          Core::apply(in, out, tb, 0u);
+          sv[u][e] = out[0];
+          cv[u][e] = out[1];
+        }
+      }
+      char *ps = y + (2 * j) * plane + head * int64_t(sizeof(raw));
+      char *pc = ps + plane;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t v = v0 + int64_t(u) * kEncodeBlock;
+        if (v < nvec) {
+          if constexpr (VEC_PATH) {
+            vstore<true>(ps, v, ST::pack(sv[u]));
+          } else {
+            reinterpret_cast<raw *>(ps)[v] = ST::store(sv[u][0]);
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t v = v0 + int64_t(u) * kEncodeBlock;
+        if (v < nvec) {
+          if constexpr (VEC_PATH) {
+            vstore<true>(pc, v, ST::pack(cv[u]));
+          } else {
+            reinterpret_cast<raw *>(pc)[v] = ST::store(cv[u][0]);
+          }
+        }
       }
     }
   }
@@ -788,16 +825,17 @@ hipError_t launch_encode(const void *x, void *y, int64_t n, int nfreq,
     int64_t head = mis ? int64_t((16u - mis) / sizeof(raw)) : 0;
     if (head > n) head = n;
     const int64_t nvec = (n - head) / VEC;
-    int64_t blocks = (nvec + kEncodeBlock - 1) / kEncodeBlock;
+    const int64_t per = int64_t(encode_unroll<ST>()) * kEncodeBlock;
+    int64_t blocks = (nvec + per - 1) / per;
     if (blocks < 1) blocks = 1;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-    return launch(encode_kernel<ST, true>, blocks, kEncodeBlock, stream, xc,
-                  yc, n, nfreq, head, nvec);
+    return launch(encode_kernel<ST, true, encode_unroll<ST>()>, blocks,
+                  kEncodeBlock, stream, xc, yc, n, nfreq, head, nvec);
   } else {
     const int64_t blocks = (n + kEncodeBlock - 1) / kEncodeBlock;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-    return launch(encode_kernel<ST, false>, blocks, kEncodeBlock, stream, xc,
-                  yc, n, nfreq, int64_t(0), n);
+    return launch(encode_kernel<ST, false, 1>, blocks, kEncodeBlock, stream,
+                  xc, yc, n, nfreq, int64_t(0), n);
   }
 }
 
