@@ -896,7 +896,8 @@ def profile_pass(args, torch, ta, dev, x, ys, yc, yt):
     2^28 FP32); copy 1 in -> 1 out (2^28 FP32, the counter calibration);
     ta_sin_fwdbwd ([128, 8192, 512] FP32); ta_sin (2^28 FP32); ta_sincos
     and ta_sin on 2^29 BF16 U[-pi, pi]; ta_sincos on 2^27 FP64
-    U[-1e6, 1e6]."""
+    U[-1e6, 1e6]; ta_sincos with the carried FP32 evaluation (2^28 FP32);
+    ta_sincos_encode (2^26 FP32 inputs, 8 frequencies)."""
     for _ in range(PROFILE_STEPS):
         ta.ta_sincos(x, ys, yc, yt)
     torch.cuda.synchronize()
@@ -936,24 +937,46 @@ def profile_pass(args, torch, ta, dev, x, ys, yc, yt):
         ta.ta_sincos(xd, ds, dc, dt)
     torch.cuda.synchronize()
     log("profiled FP64 ta_sincos")
+    del xd, ds, dc, dt
+    for _ in range(PROFILE_STEPS):
+        ta.ta_sincos_ex(x, ys, yc, yt, ta.TA_FLAG_FORCE_FP32_REDUCTION)
+    torch.cuda.synchronize()
+    log("profiled ta_sincos with the carried FP32 evaluation")
+    ne, nf = 1 << 26, 8
+    ye = torch.empty(2 * nf * ne, device=dev)
+    for _ in range(PROFILE_STEPS):
+        ta.ta_sincos_encode(x[:ne], ye, nf)
+    torch.cuda.synchronize()
+    log("profiled ta_sincos_encode (2^26 inputs, 8 frequencies)")
     print(json.dumps({"profile_pass": "done", "source_sha": source_hash()}))
 
 
 # kernel-name prefixes (the functors carry further template arguments, such
 # as the 16-bit variant flag)
 KERNELS = {
-    "sincos_tan_f32": ("F32", "FwdOp<7, false"),
+    "sincos_tan_f32": ("F32", "FwdOp<7, false, false, false, false>"),
+    "sincos_tan_f32_carried": ("F32", "FwdOp<7, false, false, true, false>"),
     "copy_1to1_f32": ("F32", "CopyOp<1, 1>"),
-    "sin_fwdbwd_f32": ("F32", "BwdOp<1, true"),
-    "sin_f32": ("F32", "FwdOp<1, false"),
-    "sincos_tan_bf16": ("BF16", "FwdOp<7, false"),
-    "sin_bf16": ("BF16", "FwdOp<1, false"),
-    "sincos_tan_f64": ("F64", "FwdOp<7, false"),
+    "sin_fwdbwd_f32": ("F32", "BwdOp<1, true, false, false>"),
+    "sin_f32": ("F32", "FwdOp<1, false, false, false, false>"),
+    "sincos_tan_bf16": ("BF16", "FwdOp<7, false, true, false, false>"),
+    "sin_bf16": ("BF16", "FwdOp<1, false, true, false, false>"),
+    "sincos_tan_f64": ("F64", "FwdOp<7, false, false, false, false>"),
+    "encode_f32": ("F32", "encode_kernel<"),
 }
-ELEMS = {"sincos_tan_f32": 1 << 28, "copy_1to1_f32": 1 << 28,
+ELEMS = {"sincos_tan_f32": 1 << 28, "sincos_tan_f32_carried": 1 << 28,
+         "copy_1to1_f32": 1 << 28,
          "sin_fwdbwd_f32": 128 * 8192 * 512, "sin_f32": 1 << 28,
          "sincos_tan_bf16": 1 << 29, "sin_bf16": 1 << 29,
-         "sincos_tan_f64": 1 << 27}
+         "sincos_tan_f64": 1 << 27, "encode_f32": 1 << 26}
+# algorithmic HBM bytes per dispatch of the profiled kernels
+ALGO_BYTES = {"sincos_tan_f32": 16 * (1 << 28),
+              "sincos_tan_f32_carried": 16 * (1 << 28),
+              "sin_fwdbwd_f32": 16 * 128 * 8192 * 512,
+              "sin_f32": 8 * (1 << 28),
+              "sincos_tan_bf16": 8 * (1 << 29), "sin_bf16": 4 * (1 << 29),
+              "sincos_tan_f64": 32 * (1 << 27),
+              "encode_f32": (4 + 64) * (1 << 26)}
 VALU_PEAK = 256 * 4 * 16 * 2.4e9  # lane-instructions/s (VALU issue)
 
 
@@ -1058,9 +1081,7 @@ def summarize(a):
                          f"{CALIB_BYTES} bytes each way")
             lines.append(f"fetch_scale: {fs:.4f}")
             lines.append(f"write_scale: {ws:.4f}")
-            for key, alg in (("sincos_tan_f32", 16 * (1 << 28)),
-                             ("sin_fwdbwd_f32", 16 * 128 * 8192 * 512),
-                             ("sincos_tan_f64", 32 * (1 << 27))):
+            for key, alg in ALGO_BYTES.items():
                 f_ = avg.get((key, "FETCH_SIZE"))
                 w_ = avg.get((key, "WRITE_SIZE"))
                 if f_ is None or w_ is None:
@@ -1093,6 +1114,42 @@ def summarize(a):
                 if cname.startswith("SQ_INSTS"):
                     extra = f" per_elem {v * 64 / n:.2f}"
                 lines.append(f"{key}_{cname}: {v:.0f}{extra}")
+        _write(out, lines)
+    elif mode == "tcc":
+        # raw TCC/EA request counts (a read pass and a write pass): bytes at
+        # the request sizes the counter descriptions give, without the
+        # copy-kernel calibration
+        rd_dir, wr_dir, out, cmd = a[1], a[2], a[3], " ".join(a[4:])
+        per = {}
+        for directory in (rd_dir, wr_dir):
+            for r in _csv_rows(directory, "counter_collection.csv"):
+                key = _which(r.get("Kernel_Name", ""))
+                if key is None:
+                    continue
+                d = per.setdefault(key, {}).setdefault(r["Counter_Name"], {})
+                disp = r.get("Dispatch_Id") or r.get("Correlation_Id")
+                d[disp] = d.get(disp, 0.0) + float(r["Counter_Value"])
+        lines = ["# rocprofv3 --pmc TCC/EA request counters (per dispatch)",
+                 f"# command: {cmd}", f"source_sha: {source_hash()}",
+                 "# read bytes: 128-byte requests (TCC_BUBBLE), 32-byte "
+                 "requests (TCC_EA0_RDREQ_32B), the rest 64-byte; write "
+                 "bytes: 64-byte (TCC_EA0_WRREQ_64B) and 32-byte requests"]
+        for key, counters in sorted(per.items()):
+            avg = {c: sum(d.values()) / len(d) for c, d in counters.items()}
+            for c, v in sorted(avg.items()):
+                lines.append(f"{key}_{c}: {v:.0f}")
+            rq, r32 = avg.get("TCC_EA0_RDREQ_sum"), avg.get("TCC_EA0_RDREQ_32B_sum")
+            b128 = avg.get("TCC_BUBBLE_sum")
+            if None not in (rq, r32, b128):
+                rd = b128 * 128 + (rq - b128 - r32) * 64 + r32 * 32
+                lines.append(f"{key}_read_bytes_by_request_size: {rd:.0f}")
+                lines.append(f"{key}_read_bytes_if_all_128B: {(rq - r32) * 128 + r32 * 32:.0f}")
+            wq, w64 = avg.get("TCC_EA0_WRREQ_sum"), avg.get("TCC_EA0_WRREQ_64B_sum")
+            if None not in (wq, w64):
+                lines.append(f"{key}_write_bytes_by_request_size: "
+                             f"{(wq - w64) * 32 + w64 * 64:.0f}")
+            if key in ALGO_BYTES:
+                lines.append(f"{key}_algorithmic_bytes: {ALGO_BYTES[key]}")
         _write(out, lines)
     else:
         raise SystemExit(f"unknown summarize mode {mode}")
