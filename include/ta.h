@@ -28,9 +28,8 @@
  *    TA_EHIP: the kernel launch failed; ta_last_hip_error() returns the
  *    hipError_t of the calling thread's last failure.
  *  - Any alignment is accepted.  When every buffer has the same address
- *    modulo 16 the body runs with vector accesses (16 bytes; 8 bytes for
- *    16-bit storage) after a scalar head and before a scalar tail; otherwise
- *    a scalar path runs.
+ *    modulo 16 the body runs with 16-byte vector accesses after a scalar
+ *    head and before a scalar tail; otherwise a scalar path runs.
  *  - Calls are reentrant and thread-safe: there is no mutable global state.
  *  - Inputs: any value.  NaN and +-Inf give NaN; sin and tan keep the sign of
  *    a zero input; cos(+-0) = 1.  Every finite input is reduced exactly

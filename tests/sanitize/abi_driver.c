@@ -61,11 +61,28 @@ int main(void) {
          TA_EOVERLAP);
   expect("builtin kind", ta_builtin_sincos(a, b, bc + 256, NULL, 16, 3, TA_F32, NULL),
          TA_EINVAL);
+  expect("builtin outputs", ta_builtin_sincos(a, b, NULL, bc + 256, 16, 0, TA_F16, NULL),
+         TA_EINVAL);
+  expect("builtin f64 kind", ta_builtin_sincos(a, b, NULL, NULL, 16, 1, TA_F64, NULL),
+         TA_EDTYPE);
+  expect("builtin fwdbwd kind",
+         ta_builtin_sin_fwdbwd(a, b, bc + 256, bc + 512, 16, 2, TA_F32, NULL), TA_EINVAL);
+  expect("builtin fwdbwd overlap",
+         ta_builtin_sin_fwdbwd(a, b, bc + 256, bc + 260, 16, 0, TA_BF16, NULL), TA_EOVERLAP);
   {
     const void *ins[1] = {a};
     void *outs[4] = {b, bc + 256, bc + 512, bc + 768};
     expect("copy n_in", ta_copy(ins, 0, outs, 1, 16, TA_F32, NULL), TA_EINVAL);
     expect("copy dtype", ta_copy(ins, 1, outs, 1, 16, (ta_dtype)9, NULL), TA_EDTYPE);
+    void *far[3] = {b, bc + 0x10000, bc + 0x20000};
+    expect("probe kind", ta_stream_probe(3, a, far, 1, 16, 0u, NULL), TA_EINVAL);
+    expect("probe flags", ta_stream_probe(1, NULL, far, 3, 16, 8u, NULL), TA_EINVAL);
+    expect("probe align", ta_stream_probe(2, (char *)a + 4, far, 1, 16, 0u, NULL),
+           TA_EINVAL);
+    expect("probe n%4", ta_stream_probe(2, a, far, 2, 18, 0u, NULL), TA_EINVAL);
+    expect("probe overlap", ta_stream_probe(2, bc + 16, far, 1, 16, 0u, NULL),
+           TA_EOVERLAP);
+    expect("probe n=0", ta_stream_probe(0, a, far, 1, 0, 7u, NULL), TA_OK);
   }
   for (int s = 0; s < 5; ++s)
     if (strncmp(ta_status_str((ta_status)s), "TA_", 3) != 0) {
