@@ -226,12 +226,15 @@ ta_status ta_copy(const void *const *in, int n_in, void *const *out,
  *   kind 1: write n_out (1..3) arrays, x unused;
  *   kind 2: copy x into n_out (1..3) arrays.
  * flags: TA_PROBE_NT_LOAD / TA_PROBE_NT_STORE (nontemporal accesses),
- * TA_PROBE_BLOCK256 (256-thread workgroups; 64 otherwise).  Overlapping
+ * TA_PROBE_BLOCK256 (256-thread workgroups; 64 otherwise),
+ * TA_PROBE_DEVICE_SCOPE (with TA_PROBE_NT_STORE only: nontemporal stores at
+ * device scope, the store the kernels' vector bodies issue).  Overlapping
  * buffers are TA_EOVERLAP. */
 enum {
   TA_PROBE_NT_LOAD = 1u,
   TA_PROBE_NT_STORE = 2u,
-  TA_PROBE_BLOCK256 = 4u
+  TA_PROBE_BLOCK256 = 4u,
+  TA_PROBE_DEVICE_SCOPE = 8u
 };
 ta_status ta_stream_probe(int kind, const void *x, void *const *out,
                           int n_out, int64_t n, uint32_t flags,

@@ -30,6 +30,7 @@ __all__ = [
     "ta_paper_sincos", "ta_sincos_encode", "ta_builtin_sincos",
     "ta_builtin_sin_fwdbwd", "ta_copy", "ta_stream_probe",
     "TA_PROBE_NT_LOAD", "TA_PROBE_NT_STORE", "TA_PROBE_BLOCK256",
+    "TA_PROBE_DEVICE_SCOPE",
     "sin", "cos", "tan", "sincos", "taylor",
     "SinFn", "CosFn", "TanFn", "SinCosFn",
     "TA_FLAG_TAN_GUARD", "TA_FLAG_LITERAL_DIVISOR",
@@ -46,6 +47,7 @@ TA_FLAG_FORCE_FP64_REDUCTION = 2
 TA_FLAG_FORCE_FP32_REDUCTION = 4
 TA_FLAG_LITERAL_DIVISOR = 8
 TA_PROBE_NT_LOAD, TA_PROBE_NT_STORE, TA_PROBE_BLOCK256 = 1, 2, 4
+TA_PROBE_DEVICE_SCOPE = 8
 _DTYPE_CODE = {torch.float32: TA_F32, torch.float16: TA_F16,
                torch.bfloat16: TA_BF16, torch.float64: TA_F64}
 

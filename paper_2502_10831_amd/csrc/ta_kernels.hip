@@ -610,6 +610,28 @@ __device__ inline void vstore(char *base, int64_t v, V x) {
   }
 }
 
+// The vector bodies' stores: nontemporal at device scope (sc1 nt).  Source
+// code reaches that cache policy only through the raw buffer store (a global
+// store takes nt alone; an inline-asm store would hide the store from the
+// compiler's hazard handling).  Each resource covers one workgroup's span of
+// one output stream (base = the span's first byte, num_records = its length),
+// so offsets stay 32-bit for any array size and the hardware's range check
+// bounds every store to the span.  Word 3 is the raw (untyped) buffer format
+// of gfx9.  Same-run on MI355X with identical outputs, against nt global
+// stores: fused FP32 sin+cos+tan 6205 -> 6277 GB/s, BF16 fused +1.7 %,
+// FP32 forward+backward +2.2 %, FP64 fused +1.2 %, single-output kernels
+// equal; plain stores were 2-10 % slower than either.
+constexpr int kBufferWord3 = 0x00020000;
+constexpr int kStoreNtDevice = 2 | 16;  // nt, sc1
+struct SpanStore {
+  __amdgpu_buffer_rsrc_t r;
+  __device__ SpanStore(char *span, int bytes)
+      : r(__builtin_amdgcn_make_buffer_rsrc(span, 0, bytes, kBufferWord3)) {}
+  __device__ void put(uint32_t byte_off, u32x4 x) const {
+    __builtin_amdgcn_raw_buffer_store_b128(x, r, byte_off, 0, kStoreNtDevice);
+  }
+};
+
 template <class ST, class Op>
 __device__ inline void scalar_element(const IoPtrs &io, int64_t i,
                                       const typename Op::Table &tb) {
@@ -625,9 +647,9 @@ __device__ inline void scalar_element(const IoPtrs &io, int64_t i,
 }
 
 // Vector body: elements [head, head + nvec*VEC) in 16-byte accesses, UNROLL
-// accesses per stream per thread, all loads issued before any compute.  The
-// workgroup with blockIdx 0 also does the scalar head [0, head) and tail
-// [head + nvec*VEC, n).
+// accesses per stream per thread, all loads issued before any compute;
+// NTS: the stores go through SpanStore.  The workgroup with blockIdx 0 also
+// does the scalar head [0, head) and tail [head + nvec*VEC, n).
 template <class ST, class Op, int BLOCK, int UNROLL, bool NTL, bool NTS,
           int MINB>
 __global__ __launch_bounds__(BLOCK, MINB) void map_vec_kernel(IoPtrs io, int64_t head,
@@ -675,8 +697,18 @@ __global__ __launch_bounds__(BLOCK, MINB) void map_vec_kernel(IoPtrs io, int64_t
         for (int k = 0; k < Op::NOUT; ++k) res[k][e] = out[k];
       }
 #pragma unroll
-      for (int k = 0; k < Op::NOUT; ++k)
-        vstore<NTS>(out_base[k], v, ST::pack(res[k]));
+      for (int k = 0; k < Op::NOUT; ++k) {
+        if constexpr (NTS) {
+          constexpr int kSpan = UNROLL * BLOCK * int(sizeof(typename ST::vec));
+          const int64_t span0 = int64_t(blockIdx.x) * (UNROLL * BLOCK);
+          const SpanStore ss(out_base[k] + span0 * int64_t(sizeof(typename ST::vec)),
+                             kSpan);
+          ss.put(uint32_t(v - span0) * uint32_t(sizeof(typename ST::vec)),
+                 ST::pack(res[k]));
+        } else {
+          vstore<false>(out_base[k], v, ST::pack(res[k]));
+        }
+      }
     }
   }
   if (blockIdx.x == 0) {
@@ -770,26 +802,26 @@ __global__ __launch_bounds__(kEncodeBlock) void encode_kernel(
       }
       char *ps = y + (2 * j) * plane + head * int64_t(sizeof(raw));
       char *pc = ps + plane;
+      if constexpr (VEC_PATH) {
+        // this group's span of each plane, one SpanStore each
+        constexpr int kVB = int(sizeof(typename ST::vec));
+        const int64_t span0 = int64_t(blockIdx.x) * (U * kEncodeBlock);
+        const SpanStore ss(ps + span0 * kVB, U * kEncodeBlock * kVB);
+        const SpanStore sc(pc + span0 * kVB, U * kEncodeBlock * kVB);
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int64_t v = v0 + int64_t(u) * kEncodeBlock;
-        if (v < nvec) {
-          if constexpr (VEC_PATH) {
-            vstore<true>(ps, v, ST::pack(sv[u]));
-          } else {
-            reinterpret_cast<raw *>(ps)[v] = ST::store(sv[u][0]);
-          }
+        for (int u = 0; u < U; ++u) {
+          const int64_t v = v0 + int64_t(u) * kEncodeBlock;
+          if (v < nvec) ss.put(uint32_t(v - span0) * kVB, ST::pack(sv[u]));
         }
-      }
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int64_t v = v0 + int64_t(u) * kEncodeBlock;
-        if (v < nvec) {
-          if constexpr (VEC_PATH) {
-            vstore<true>(pc, v, ST::pack(cv[u]));
-          } else {
-            reinterpret_cast<raw *>(pc)[v] = ST::store(cv[u][0]);
-          }
+        for (int u = 0; u < U; ++u) {
+          const int64_t v = v0 + int64_t(u) * kEncodeBlock;
+          if (v < nvec) sc.put(uint32_t(v - span0) * kVB, ST::pack(cv[u]));
+        }
+      } else {
+        if (v0 < nvec) {
+          reinterpret_cast<raw *>(ps)[v0] = ST::store(sv[0][0]);
+          reinterpret_cast<raw *>(pc)[v0] = ST::store(cv[0][0]);
         }
       }
     }
@@ -859,8 +891,9 @@ __global__ __launch_bounds__(BLOCK) void probe_read_kernel(const char *x,
     if (acc == key) sink[blockIdx.x & 1023u] = acc;
   }
 }
-// Writes (NIN = 0) or copies (NIN = 1) into NOUT arrays.
-template <int BLOCK, int NIN, int NOUT, bool NTL, bool NTS>
+// Writes (NIN = 0) or copies (NIN = 1) into NOUT arrays.  STORE: 0 plain,
+// 1 nontemporal, 2 nontemporal at device scope (the kernels' SpanStore).
+template <int BLOCK, int NIN, int NOUT, bool NTL, int STORE>
 __global__ __launch_bounds__(BLOCK) void probe_stream_kernel(IoPtrs io,
                                                              int64_t nvec) {
   const int64_t v = int64_t(blockIdx.x) * BLOCK + threadIdx.x;
@@ -868,11 +901,19 @@ __global__ __launch_bounds__(BLOCK) void probe_stream_kernel(IoPtrs io,
     u32x4 w = {uint32_t(v), 0u, 0u, 0u};
     if constexpr (NIN == 1) w = vload<NTL>(io.in[0], v);
 #pragma unroll
-    for (int k = 0; k < NOUT; ++k) vstore<NTS>(io.out[k], v, w);
+    for (int k = 0; k < NOUT; ++k) {
+      if constexpr (STORE == 2) {
+        const int64_t span0 = int64_t(blockIdx.x) * BLOCK;
+        const SpanStore ss(io.out[k] + span0 * 16, BLOCK * 16);
+        ss.put(uint32_t(v - span0) * 16u, w);
+      } else {
+        vstore<STORE == 1>(io.out[k], v, w);
+      }
+    }
   }
 }
 
-template <int BLOCK, bool NTL, bool NTS>
+template <int BLOCK, bool NTL, int STORE>
 hipError_t launch_probe(int kind, const void *x, void *const *out, int n_out,
                         int64_t nvec, hipStream_t s) {
   const int64_t blocks = (nvec + BLOCK - 1) / BLOCK;
@@ -885,12 +926,28 @@ hipError_t launch_probe(int kind, const void *x, void *const *out, int n_out,
   io.in[0] = static_cast<const char *>(x);
   for (int k = 0; k < n_out; ++k) io.out[k] = static_cast<char *>(out[k]);
   switch ((kind == 2 ? 4 : 0) + n_out) {
-    case 1: return launch(probe_stream_kernel<BLOCK, 0, 1, NTL, NTS>, blocks, BLOCK, s, io, nvec);
-    case 2: return launch(probe_stream_kernel<BLOCK, 0, 2, NTL, NTS>, blocks, BLOCK, s, io, nvec);
-    case 3: return launch(probe_stream_kernel<BLOCK, 0, 3, NTL, NTS>, blocks, BLOCK, s, io, nvec);
-    case 5: return launch(probe_stream_kernel<BLOCK, 1, 1, NTL, NTS>, blocks, BLOCK, s, io, nvec);
-    case 6: return launch(probe_stream_kernel<BLOCK, 1, 2, NTL, NTS>, blocks, BLOCK, s, io, nvec);
-    default: return launch(probe_stream_kernel<BLOCK, 1, 3, NTL, NTS>, blocks, BLOCK, s, io, nvec);
+    case 1: return launch(probe_stream_kernel<BLOCK, 0, 1, NTL, STORE>, blocks, BLOCK, s, io, nvec);
+    case 2: return launch(probe_stream_kernel<BLOCK, 0, 2, NTL, STORE>, blocks, BLOCK, s, io, nvec);
+    case 3: return launch(probe_stream_kernel<BLOCK, 0, 3, NTL, STORE>, blocks, BLOCK, s, io, nvec);
+    case 5: return launch(probe_stream_kernel<BLOCK, 1, 1, NTL, STORE>, blocks, BLOCK, s, io, nvec);
+    case 6: return launch(probe_stream_kernel<BLOCK, 1, 2, NTL, STORE>, blocks, BLOCK, s, io, nvec);
+    default: return launch(probe_stream_kernel<BLOCK, 1, 3, NTL, STORE>, blocks, BLOCK, s, io, nvec);
+  }
+}
+template <int BLOCK>
+hipError_t launch_probe_flags(int kind, const void *x, void *const *out,
+                              int n_out, int64_t nvec, uint32_t flags,
+                              hipStream_t s) {
+  const bool ntl = flags & TA_PROBE_NT_LOAD;
+  const int store = (flags & TA_PROBE_NT_STORE)
+                        ? ((flags & TA_PROBE_DEVICE_SCOPE) ? 2 : 1) : 0;
+  switch ((ntl ? 3 : 0) + store) {
+    case 0: return launch_probe<BLOCK, false, 0>(kind, x, out, n_out, nvec, s);
+    case 1: return launch_probe<BLOCK, false, 1>(kind, x, out, n_out, nvec, s);
+    case 2: return launch_probe<BLOCK, false, 2>(kind, x, out, n_out, nvec, s);
+    case 3: return launch_probe<BLOCK, true, 0>(kind, x, out, n_out, nvec, s);
+    case 4: return launch_probe<BLOCK, true, 1>(kind, x, out, n_out, nvec, s);
+    default: return launch_probe<BLOCK, true, 2>(kind, x, out, n_out, nvec, s);
   }
 }
 
@@ -1261,7 +1318,9 @@ ta_status ta_stream_probe(int kind, const void *x, void *const *out,
                           hipStream_t s) {
   if (kind < 0 || kind > 2 || n < 0) return TA_EINVAL;
   if (flags & ~uint32_t(TA_PROBE_NT_LOAD | TA_PROBE_NT_STORE |
-                       TA_PROBE_BLOCK256))
+                       TA_PROBE_BLOCK256 | TA_PROBE_DEVICE_SCOPE))
+    return TA_EINVAL;
+  if ((flags & TA_PROBE_DEVICE_SCOPE) && !(flags & TA_PROBE_NT_STORE))
     return TA_EINVAL;
   if (kind == 0 ? n_out != 1 : (n_out < 1 || n_out > 3)) return TA_EINVAL;
   if (n == 0) return TA_OK;
@@ -1282,19 +1341,10 @@ ta_status ta_stream_probe(int kind, const void *x, void *const *out,
     }
   }
   const int64_t nvec = n / 4;
-  const bool ntl = flags & TA_PROBE_NT_LOAD, nts = flags & TA_PROBE_NT_STORE;
-  hipError_t e;
-  if (flags & TA_PROBE_BLOCK256) {
-    e = ntl ? (nts ? launch_probe<256, true, true>(kind, x, out, n_out, nvec, s)
-                   : launch_probe<256, true, false>(kind, x, out, n_out, nvec, s))
-            : (nts ? launch_probe<256, false, true>(kind, x, out, n_out, nvec, s)
-                   : launch_probe<256, false, false>(kind, x, out, n_out, nvec, s));
-  } else {
-    e = ntl ? (nts ? launch_probe<64, true, true>(kind, x, out, n_out, nvec, s)
-                   : launch_probe<64, true, false>(kind, x, out, n_out, nvec, s))
-            : (nts ? launch_probe<64, false, true>(kind, x, out, n_out, nvec, s)
-                   : launch_probe<64, false, false>(kind, x, out, n_out, nvec, s));
-  }
+  const hipError_t e =
+      (flags & TA_PROBE_BLOCK256)
+          ? launch_probe_flags<256>(kind, x, out, n_out, nvec, flags, s)
+          : launch_probe_flags<64>(kind, x, out, n_out, nvec, flags, s);
   return finish(e);
 }
 

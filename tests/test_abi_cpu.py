@@ -167,7 +167,8 @@ def test_stream_probe_validation(lib):
     assert f(2, A, outs, 4, 16, 0, None) == EINVAL
     assert f(2, A, outs, 1, 18, 0, None) == EINVAL          # n % 4
     assert f(2, A + 4, outs, 1, 16, 0, None) == EINVAL      # alignment
-    assert f(1, None, outs, 3, 16, 8, None) == EINVAL       # unknown flag
+    assert f(1, None, outs, 3, 16, 16, None) == EINVAL      # unknown flag
+    assert f(1, None, outs, 3, 16, 8, None) == EINVAL       # scope w/o nt
     assert f(2, A, outs, 1, -4, 0, None) == EINVAL
     assert f(2, None, outs, 1, 16, 0, None) == EINVAL       # copy needs x
     assert f(2, B + 16, outs, 1, 16, 0, None) == EOVERLAP

@@ -943,13 +943,15 @@ def test_builtin_comparators_all_shapes(dev):
 def test_stream_probes(dev):
     """The bandwidth probes stream what they claim: the write probe stores
     the vector index in the first word of each 16-byte vector and zeros in
-    the others, the copy probe copies, the read probe runs; every flag
-    combination."""
+    the others, the copy probe copies, the read probe runs; every valid flag
+    combination (device scope only with nontemporal stores)."""
     n = (1 << 20) + 4096
     x = torch.randn(n, device=dev)
     sink = torch.zeros(1024, dtype=torch.int32, device=dev)
     idx = torch.arange(n // 4, device=dev, dtype=torch.int64).to(torch.int32)
-    for flags in range(8):
+    for flags in range(16):
+        if (flags & ta.TA_PROBE_DEVICE_SCOPE) and not (flags & ta.TA_PROBE_NT_STORE):
+            continue
         outs = [torch.full((n,), 7.0, device=dev) for _ in range(3)]
         ta.ta_stream_probe(0, x, [sink.view(torch.float32)], flags)
         for k in (1, 2, 3):
