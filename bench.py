@@ -372,8 +372,18 @@ def stream_ceiling(x, ys, yc, yt, n, args, torch, ta, kernel_ms):
             1, x, [ys, yc, yt], P.TA_PROBE_BLOCK256)),
         ("write_only_1_array_nt", 4, lambda: P.ta_stream_probe(
             1, x, [ys], P.TA_PROBE_BLOCK256 | P.TA_PROBE_NT_STORE)),
+        ("write_only_3_arrays_nt_device_scope", 12, lambda: P.ta_stream_probe(
+            1, x, [ys, yc, yt], P.TA_PROBE_BLOCK256 | P.TA_PROBE_NT_STORE |
+            P.TA_PROBE_DEVICE_SCOPE)),
         ("copy_1to1", 8, lambda: P.ta_copy([x], [ys])),
-        ("copy_1to3_64thr_nt_store", 16, lambda: P.ta_copy([x], [ys, yc, yt])),
+        # ta_copy: the kernels' own skeleton and store (64-thread groups)
+        ("copy_1to3_64thr_nt_device_scope_store", 16,
+         lambda: P.ta_copy([x], [ys, yc, yt])),
+        ("copy_1to3_256thr_nt_device_scope_store", 16, lambda: P.ta_stream_probe(
+            2, x, [ys, yc, yt], P.TA_PROBE_BLOCK256 | P.TA_PROBE_NT_STORE |
+            P.TA_PROBE_DEVICE_SCOPE)),
+        ("copy_1to3_64thr_nt_store", 16, lambda: P.ta_stream_probe(
+            2, x, [ys, yc, yt], P.TA_PROBE_NT_STORE)),
         ("copy_1to3_256thr_nt_store", 16, lambda: P.ta_stream_probe(
             2, x, [ys, yc, yt], P.TA_PROBE_BLOCK256 | P.TA_PROBE_NT_STORE)),
         ("copy_1to3_256thr_nt_load_store", 16, lambda: P.ta_stream_probe(

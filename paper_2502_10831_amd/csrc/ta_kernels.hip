@@ -538,11 +538,12 @@ struct IoPtrs {
 //   two FP32/FP64 inputs, one output (backward): 128 threads, two accesses,
 //     nontemporal loads and stores; two outputs (fused forward+backward):
 //     one access;
-//   16-bit storage, nontemporal loads and stores: one input and one output,
-//     128 threads and two accesses per thread (BF16 sin 1625 Gelem/s against
-//     1495 with four 8-byte accesses); every other category 256 threads and
-//     one access (within 1-3 % of the best 8-byte shapes for several
-//     outputs, 2-5 % above them for the backward).
+//   16-bit storage: one input and one output, 128 threads and two accesses
+//     per thread with nontemporal loads (BF16 sin 1625 Gelem/s against 1495
+//     with four 8-byte accesses); every other category 256 threads and one
+//     access, with plain loads for one input and several outputs (BF16
+//     sin+cos+tan 6.28 against 6.19 TB/s with nontemporal loads) and
+//     nontemporal loads for two or more inputs.
 struct Shape {
   int block, unroll;
   bool nt_load, nt_store;
@@ -556,6 +557,7 @@ constexpr Shape kShapeLight{128, 1, false, true};
 constexpr Shape kShapeTwoIn{128, 1, true, true};
 constexpr Shape kShapeTwoIn1{128, 2, true, true};
 constexpr Shape kShapeHalfSingle{128, 2, true, true};
+constexpr Shape kShapeHalfMulti{256, 1, false, true};
 constexpr Shape kShapeHalf{256, 1, true, true};
 // The copy comparators (the HBM ceiling a kernel is compared with): one
 // wave per workgroup, the fastest plain copy of 1 -> 3 and 2 -> 2 FP32
@@ -577,8 +579,11 @@ template <class ST, class Op>
 constexpr Shape shape_for() {
   if (sizeof(typename ST::raw) >= 4 && is_copy<Op>::value)
     return kShapeCopy;
-  if (sizeof(typename ST::raw) == 2)
-    return Op::NIN == 1 && Op::NOUT == 1 ? kShapeHalfSingle : kShapeHalf;
+  if (sizeof(typename ST::raw) == 2) {
+    if (Op::NIN == 1)
+      return Op::NOUT == 1 ? kShapeHalfSingle : kShapeHalfMulti;
+    return kShapeHalf;
+  }
   if (Op::NIN >= 2)
     return Op::NOUT == 1 ? kShapeTwoIn1 : kShapeTwoIn;
   if (Op::NOUT >= 2)

@@ -73,3 +73,26 @@ def test_trace_summary_on_a_synthetic_trace(tmp_path):
     assert (f"sincos_tan_f32_headline_timed: the last {steps} of the first "
             f"{warm + steps} back-to-back dispatches, average_ns 700000") in text
     assert f"source_sha: {bench.source_hash()}" in text
+
+
+def test_error_helpers_match_the_format_ulps():
+    """bench._ulp_of gives the spacing of the binary format at |y| (FP32,
+    BF16, FP16 and FP64 parameters against numpy's own spacing), and
+    _err_stats reports max |got - ref| and its size in those ulps."""
+    import numpy as np
+    rng = np.random.default_rng(5)
+    y = np.concatenate([rng.uniform(-4, 4, 1000), [1.0, 0.5, 2.0 ** -130]])
+    for dt, mant, emin in ((np.float32, 23, -126), (np.float16, 10, -14),
+                           (np.float64, 52, -1022)):
+        yd = y.astype(dt)
+        want = np.spacing(np.abs(yd)).astype(np.float64)
+        got = bench._ulp_of(yd.astype(np.float64), mant, emin)
+        keep = np.abs(yd) > 0
+        np.testing.assert_array_equal(got[keep], want[keep])
+    # BF16: 7 stored bits, FP32's exponent range
+    assert bench._ulp_of(np.array([1.0, 3.0]), 7, -126).tolist() == [2.0 ** -7, 2.0 ** -6]
+    ref = np.array([1.0, -0.75, np.nan, 0.25])
+    got = np.array([1.0 + 2.0 ** -22, -0.75, np.nan, 0.25 - 2.0 ** -26])
+    st = bench._err_stats(got, ref, 23, -126)
+    assert st["max_abs"] == 2.0 ** -22
+    assert st["max_ulp"] == 2.0
