@@ -27,6 +27,8 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, AMD published
 METRIC = ("Gelem/s + % HBM peak, ta_sincos FP32 2^28 vs HIP sinf/cosf at "
           "stated max err")
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "ta_sincos_tan_f32_2p28_pmc.txt")
+SQ_SUMMARY = "ta_kernels_f32_bf16_f64_sq_instructions.txt"
+SQ_CLASS_SUMMARY = "ta_kernels_valu_instruction_classes.txt"
 WARM_S = 0.3  # seconds of untimed load before each secondary measurement
 
 
@@ -92,6 +94,28 @@ def time_launches(fn, steps, warmup, torch, warm_seconds=0.0):
     per = [a.elapsed_time(b) for a, b in ev]
     total = ev[0][0].elapsed_time(ev[-1][1])
     return per, total, wall
+
+
+def interleaved(fa, fb, rounds, launches, torch):
+    """Two launch sequences timed in alternating blocks on the same stream
+    (ten untimed launches, then `launches` timed with one event pair), so
+    that both see the same clock and memory state; per-block ms per launch
+    of each, and the median over rounds of time(fb) / time(fa)."""
+    ta_ms, tb_ms = [], []
+    for _ in range(rounds):
+        for fn, acc in ((fa, ta_ms), (fb, tb_ms)):
+            for _ in range(10):
+                fn()
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(launches):
+                fn()
+            b.record()
+            torch.cuda.synchronize()
+            acc.append(a.elapsed_time(b) / launches)
+    ratios = sorted(y / x for x, y in zip(ta_ms, tb_ms))
+    return ta_ms, tb_ms, ratios[len(ratios) // 2]
 
 
 def pmc_traffic():
@@ -179,6 +203,11 @@ def main():
     cper, _, _ = time_launches(lambda: ta.ta_copy([x], [ys, yc, yt]),
                                args.steps, args.warmup, torch, WARM_S)
     copy_gbs = 16 * n / (sum(cper) / len(cper) * 1e-3) / 1e9
+    # the same two kernels again in alternating blocks: their ratio without
+    # the drift of the GPU's clock between two separately timed loops
+    log("timing ta_sincos and copy 1 -> 3 interleaved")
+    ik, ic, iratio = interleaved(
+        step, lambda: ta.ta_copy([x], [ys, yc, yt]), 8, 30, torch)
     step()
     torch.cuda.synchronize()
     gelem = n / (ms_per_step * 1e-3) / 1e9
@@ -216,19 +245,21 @@ def main():
             "algorithmic_bytes_per_launch": alg_bytes,
             "copy_1in_3out_gbs": round(copy_gbs, 1),
             "frac_of_copy": round(achieved / copy_gbs, 4),
+            "interleaved_with_copy": {
+                "rounds": 8, "launches_per_block": 30,
+                "kernel_gbs_median": round(
+                    16 * n / (sorted(ik)[4] * 1e-3) / 1e9, 1),
+                "copy_gbs_median": round(
+                    16 * n / (sorted(ic)[4] * 1e-3) / 1e9, 1),
+                "frac_of_copy_median": round(iratio, 4)},
         },
     }
     if traffic:
         out["roofline"]["traffic_gbs"] = round(
             traffic / (kernel_ms * 1e-3) / 1e9, 1)
-    valu = sq_per_elem().get("sincos_tan_f32")
-    if valu:
-        lane = valu * n / (kernel_ms * 1e-3)
-        out["roofline"]["valu_issue"] = {
-            "valu_per_elem": valu, "achieved": round(lane / 1e12, 2),
-            "peak": round(VALU_PEAK / 1e12, 2),
-            "unit": "1e12 VALU lane-instructions/s",
-            "frac": round(lane / VALU_PEAK, 3)}
+    alu = valu_roofline("sincos_tan_f32", n / (kernel_ms * 1e-3))
+    if alu:
+        out["roofline"]["valu"] = alu
     host_wall_ms = wall / args.steps
     out["timing_note"] = {"host_wall_ms_per_step": round(host_wall_ms, 4)}
 
@@ -718,10 +749,10 @@ def paper_protocol(torch, ta, dev, dtype=None, n_angles=1000, copies=1 << 22,
     return out
 
 
-def sq_per_elem():
-    """VALU instructions per element from the committed SQ summary (None
-    when it was taken on other kernel sources)."""
-    path = os.path.join(ROOT, "profiles", "ta_kernels_f32_bf16_f64_sq_instructions.txt")
+def _sq_summary(name):
+    """per_elem values of a committed SQ summary, keyed (kernel, counter),
+    or {} when it is missing or was taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return {}
     out, sha = {}, None
@@ -729,10 +760,72 @@ def sq_per_elem():
         for line in f:
             if line.startswith("source_sha:"):
                 sha = line.split(":", 1)[1].strip()
-            if "_SQ_INSTS_VALU:" in line and "per_elem" in line:
-                key = line.split("_SQ_INSTS_VALU:")[0]
-                out[key] = float(line.rsplit("per_elem", 1)[1])
+            if "_SQ_INSTS_" in line and "per_elem" in line:
+                head = line.split(":", 1)[0]
+                key, cname = head.split("_SQ_INSTS_", 1)
+                out[(key, "SQ_INSTS_" + cname)] = float(line.rsplit("per_elem", 1)[1])
     return out if sha == source_hash() else {}
+
+
+def sq_per_elem():
+    """VALU instructions per element from the committed SQ summary (None
+    when it was taken on other kernel sources)."""
+    d = _sq_summary(SQ_SUMMARY)
+    return {k: v for (k, c), v in d.items() if c == "SQ_INSTS_VALU"}
+
+
+# SIMD cycles one wave64 VALU instruction occupies, by class, measured on
+# MI355X with 8 independent chains per wave and 8 waves per SIMD: FP32
+# add/mul/fma with VGPR or inline-constant operands 2 (2.1-2.4 measured:
+# the 157.3 TFLOP/s FP32 vector rate, without packed math), the same with an
+# SGPR operand 4, FP64 add/mul/fma and conversions 4, v_rsq/v_rcp_f32 8;
+# integer and other instructions 2 (v_lshrrev, v_add_u32, v_bitop3 with VGPR
+# operands) to 4 (v_lshl_add_u32, v_xad_u32, SGPR operands).
+VALU_CYCLES = {"f32": 2, "f64_cvt": 4, "trans": 8, "other_lo": 2, "other_hi": 4}
+SIMD_CYCLES_PER_S = 256 * 4 * 2.4e9  # 256 CUs x 4 SIMDs x 2.4 GHz
+
+
+def valu_cycles_per_elem(kernel):
+    """Modelled VALU SIMD cycles per element of a profiled kernel from its
+    instruction classes (two committed SQ summaries): (mid, lo, hi), the
+    other instructions at 3, 2 and 4 cycles, FP32 arithmetic at 2 (at 4 in
+    hi, for SGPR operands); None without both summaries."""
+    a, b = _sq_summary(SQ_SUMMARY), _sq_summary(SQ_CLASS_SUMMARY)
+    g = lambda d, c: d.get((kernel, c))
+    total = g(a, "SQ_INSTS_VALU")
+    need = [g(b, c) for c in ("SQ_INSTS_VALU_FMA_F32", "SQ_INSTS_VALU_ADD_F32",
+                              "SQ_INSTS_VALU_MUL_F32", "SQ_INSTS_VALU_TRANS_F32",
+                              "SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_MUL_F64",
+                              "SQ_INSTS_VALU_INT64")]
+    fma64, cvt = g(a, "SQ_INSTS_VALU_FMA_F64"), g(a, "SQ_INSTS_VALU_CVT")
+    if total is None or fma64 is None or cvt is None or any(v is None for v in need):
+        return None
+    f32 = need[0] + need[1] + need[2]
+    trans = need[3]
+    c4 = fma64 + need[4] + need[5] + cvt + need[6]
+    rest = max(0.0, total - f32 - trans - c4)
+    fixed = VALU_CYCLES["f64_cvt"] * c4 + VALU_CYCLES["trans"] * trans
+    lo = (fixed + 2 * f32 + VALU_CYCLES["other_lo"] * rest) / 64
+    hi = (fixed + 4 * f32 + VALU_CYCLES["other_hi"] * rest) / 64
+    mid = (fixed + 2 * f32 + 3 * rest) / 64
+    return mid, lo, hi
+
+
+def valu_roofline(kernel, elems_per_s):
+    """The ALU roofline of a kernel: modelled VALU SIMD cycles used per
+    second against the 2.46e12 the chip has."""
+    c = valu_cycles_per_elem(kernel)
+    valu = sq_per_elem().get(kernel)
+    if c is None:
+        return None
+    mid, lo, hi = c
+    return {"bound": "alu", "achieved": round(elems_per_s * mid / 1e12, 3),
+            "peak": round(SIMD_CYCLES_PER_S / 1e12, 3),
+            "unit": "1e12 VALU SIMD-cycles/s",
+            "frac": round(elems_per_s * mid / SIMD_CYCLES_PER_S, 3),
+            "frac_range": [round(elems_per_s * lo / SIMD_CYCLES_PER_S, 3),
+                           round(elems_per_s * hi / SIMD_CYCLES_PER_S, 3)],
+            "valu_per_elem": valu, "cycles_per_elem": round(mid, 3)}
 
 
 def other_workloads(args, torch, ta, dev):
@@ -743,7 +836,6 @@ def other_workloads(args, torch, ta, dev):
     and the [64, 4096, 256] activation (FP32 and BF16)."""
     res = {}
     steps = max(5, args.steps // 2)
-    valu = sq_per_elem()
     gen = torch.Generator(device=dev).manual_seed(2024873)
 
     def timed(fn):
@@ -800,14 +892,9 @@ def other_workloads(args, torch, ta, dev):
                           "tan": pt.double().cpu().numpy()})}
         for key, kind, ms in (("sincos_tan", "sincos_tan_bf16", ms3),
                               ("sin", "sin_bf16", ms1)):
-            if tag == "bf16" and kind in valu:
-                lane_instr = valu[kind] * n / (ms * 1e-3)
-                entry[key]["roofline_alu"] = {
-                    "bound": "alu", "achieved": round(lane_instr / 1e12, 2),
-                    "peak": round(VALU_PEAK / 1e12, 2),
-                    "unit": "1e12 VALU lane-instructions/s",
-                    "frac": round(lane_instr / VALU_PEAK, 3),
-                    "valu_per_elem": valu[kind]}
+            alu = valu_roofline(kind, n / (ms * 1e-3)) if tag == "bf16" else None
+            if alu:
+                entry[key]["roofline_alu"] = alu
         # every input of this workload is one of the 16-bit patterns in
         # [-pi, pi]: the errors over all of them are the workload's errors
         pat = torch.arange(1 << 16, dtype=torch.int32, device=dev).to(
@@ -987,7 +1074,6 @@ ALGO_BYTES = {"sincos_tan_f32": 16 * (1 << 28),
               "sincos_tan_bf16": 8 * (1 << 29), "sin_bf16": 4 * (1 << 29),
               "sincos_tan_f64": 32 * (1 << 27),
               "encode_f32": (4 + 64) * (1 << 26)}
-VALU_PEAK = 256 * 4 * 16 * 2.4e9  # lane-instructions/s (VALU issue)
 
 
 def _csv_rows(directory, suffix):

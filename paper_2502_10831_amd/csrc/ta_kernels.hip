@@ -525,38 +525,50 @@ struct IoPtrs {
 // Launch shape of the vector body, per kernel category, chosen by timing on
 // MI355X (2^27-2^29 elements):
 //   one input, several outputs: one 16-byte access per stream per thread,
-//     nontemporal stores; 256 threads for FP32 (7 % above 128), 128 for
-//     FP64 (3 % above 256);
-//   one FP32 output, the method (LDS table): two accesses per thread,
-//     nontemporal loads and stores, and at most 64 VGPRs (eight workgroups
-//     per CU: eight waves per SIMD; 5-6 % above four accesses in 86 VGPRs;
-//     the registers spilled are those of the rare large-argument branch);
+//     plain loads and device-scope nontemporal stores; 256 threads for FP32
+//     (7 % above 128), 128 for FP64 (3 % above 256);
+//   one FP32 output, the method (LDS table): 128 threads, two accesses per
+//     thread, nontemporal loads and stores, at most 64 VGPRs (eight waves per
+//     SIMD; the registers spilled are those of the rare large-argument
+//     branch), the loads issued before the table fill (below): 819 Gelem/s
+//     against 789 for 256 threads with the fill first; 64 threads 763, four
+//     accesses 766, 72 VGPRs (seven waves) 804-808;
 //     one FP64 output, the tan guard or the paper-literal arithmetic:
 //     four accesses;
-//   one FP32/FP64 output, light functors (Taylor, copy): one access, 128
-//     threads (2 % above 256);
+//   one FP32/FP64 output, light functors (Taylor, the built-ins; no table):
+//     one access, 128 threads (2 % above 256), nontemporal loads (sinf 860
+//     Gelem/s against 827 with plain loads);
 //   two FP32/FP64 inputs, one output (backward): 128 threads, two accesses,
 //     nontemporal loads and stores; two outputs (fused forward+backward):
 //     one access;
 //   16-bit storage: one input and one output, 128 threads and two accesses
-//     per thread with nontemporal loads (BF16 sin 1625 Gelem/s against 1495
-//     with four 8-byte accesses); every other category 256 threads and one
-//     access, with plain loads for one input and several outputs (BF16
-//     sin+cos+tan 6.28 against 6.19 TB/s with nontemporal loads) and
-//     nontemporal loads for two or more inputs.
+//     per thread with nontemporal loads, loads before the fill (BF16 sin
+//     1663 Gelem/s against 1634 with the fill first and 1495 with four
+//     8-byte accesses); every other category 256 threads and one access, with
+//     plain loads for one input and several outputs (BF16 sin+cos+tan 6.28
+//     against 6.19 TB/s with nontemporal loads) and nontemporal loads for two
+//     or more inputs.
+// loads_first: the kernel issues its loads, then fills the LDS table and
+// waits at the barrier, so the fill overlaps the loads' latency.  That pays
+// for one input and one output (FP32 sin +2.5-3.8 %, BF16 sin +1.7-2.2 %,
+// FP16 sin +0.6 %); the several-output kernels fill first (issuing their
+// loads earlier measured sin+cos+tan -4.2 %, sin+cos -3.6 %, BF16
+// sin+cos+tan -0.3 %, FP64 sin+cos+tan -0.7 %), and the backward and FP64
+// single-output kernels showed no difference either way.
 struct Shape {
   int block, unroll;
   bool nt_load, nt_store;
-  int min_blocks = 1;  // __launch_bounds__ minimum workgroups per CU
+  int min_blocks = 1;  // __launch_bounds__ minimum waves per SIMD
+  bool loads_first = false;
 };
 constexpr Shape kShapeMulti{256, 1, false, true};
-constexpr Shape kShapeSingle{256, 2, true, true, 8};
+constexpr Shape kShapeSingle{128, 2, true, true, 8, true};
 constexpr Shape kShapeSingleWide{256, 4, true, true};
 constexpr Shape kShapeMulti64{128, 1, false, true};
-constexpr Shape kShapeLight{128, 1, false, true};
+constexpr Shape kShapeLight{128, 1, true, true};
 constexpr Shape kShapeTwoIn{128, 1, true, true};
 constexpr Shape kShapeTwoIn1{128, 2, true, true};
-constexpr Shape kShapeHalfSingle{128, 2, true, true};
+constexpr Shape kShapeHalfSingle{128, 2, true, true, 1, true};
 constexpr Shape kShapeHalfMulti{256, 1, false, true};
 constexpr Shape kShapeHalf{256, 1, true, true};
 // The copy comparators (the HBM ceiling a kernel is compared with): one
@@ -652,17 +664,18 @@ __device__ inline void scalar_element(const IoPtrs &io, int64_t i,
 }
 
 // Vector body: elements [head, head + nvec*VEC) in 16-byte accesses, UNROLL
-// accesses per stream per thread, all loads issued before any compute;
-// NTS: the stores go through SpanStore.  The workgroup with blockIdx 0 also
-// does the scalar head [0, head) and tail [head + nvec*VEC, n).
+// accesses per stream per thread, all loads issued before any compute (LF:
+// also before the table fill and its barrier); NTS: the stores go through
+// SpanStore.  The workgroup with blockIdx 0 also does the scalar head
+// [0, head) and tail [head + nvec*VEC, n).
 template <class ST, class Op, int BLOCK, int UNROLL, bool NTL, bool NTS,
-          int MINB>
+          int MINB, bool LF>
 __global__ __launch_bounds__(BLOCK, MINB) void map_vec_kernel(IoPtrs io, int64_t head,
                                                         int64_t nvec, int64_t n) {
   using raw = typename ST::raw;
   constexpr int VEC = ST::kVec;
   __shared__ typename Op::Table tb;
-  if constexpr (Op::Table::kUsed) {
+  if constexpr (Op::Table::kUsed && !LF) {
     Op::Table::init(tb);
     __syncthreads();
   }
@@ -683,6 +696,10 @@ __global__ __launch_bounds__(BLOCK, MINB) void map_vec_kernel(IoPtrs io, int64_t
 #pragma unroll
       for (int k = 0; k < Op::NIN; ++k) in_raw[u][k] = vload<NTL, typename ST::vec>(in_base[k], v);
     }
+  }
+  if constexpr (Op::Table::kUsed && LF) {
+    Op::Table::init(tb);
+    __syncthreads();
   }
 #pragma unroll
   for (int u = 0; u < UNROLL; ++u) {
@@ -750,8 +767,8 @@ hipError_t launch(void (*kernel)(KArgs...), int64_t blocks, int threads,
 // contiguous to each plane and issues the U stores of one plane together;
 // otherwise one element per lane.  128-thread groups with nontemporal stores.
 // At 2^26 FP32 inputs and 8 frequencies, U = 4 moves 6.47 TB/s against 6.02
-// for U = 1 (0.94 of the same-run write-only fill); a launch bound of two or
-// four groups per CU made the compiler spill and fall to ~0.95 TB/s.
+// for U = 1 (0.94 of the same-run write-only fill); launch bounds asking for
+// two or four waves per SIMD made the compiler spill and fall to ~0.95 TB/s.
 constexpr int kEncodeBlock = 128;
 template <class ST>
 constexpr int encode_unroll() {
@@ -972,6 +989,15 @@ __global__ __launch_bounds__(kScalarBlock) void map_scalar_kernel(IoPtrs io,
     scalar_element<ST, Op>(io, i, tb);
 }
 
+// One input stream of at most 256 MiB (the Infinity Cache's size) is read
+// with plain loads whatever the shape says: a launch after the one that wrote
+// or read the array then hits in the cache, which nontemporal loads would
+// pass by.  Single-output kernels on MI355X, arrays re-read launch after
+// launch: plain loads +7-34 % up to 256 MiB of input (FP32 sin at 2^23: 773
+// against 651 Gelem/s; FP64 sin at 2^22: 400 against 297), nontemporal loads
+// +2-4 % from 512 MiB; below 32 MiB in and out either is the same.
+constexpr int64_t kCacheResidentBytes = int64_t(256) << 20;
+
 template <class ST, class Op>
 hipError_t launch_map(const void *const *in, void *const *out, int64_t n,
                       hipStream_t stream, uint32_t flags) {
@@ -998,9 +1024,16 @@ hipError_t launch_map(const void *const *in, void *const *out, int64_t n,
     int64_t blocks = (nvec + per_block - 1) / per_block;
     if (blocks < 1) blocks = 1;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    if constexpr (sh.nt_load && Op::NIN == 1) {
+      if (n <= kCacheResidentBytes / int64_t(sizeof(raw)))
+        return launch(
+            map_vec_kernel<ST, Op, sh.block, sh.unroll, false, sh.nt_store,
+                           sh.min_blocks, sh.loads_first>,
+            blocks, sh.block, stream, io, head, nvec, n);
+    }
     return launch(
         map_vec_kernel<ST, Op, sh.block, sh.unroll, sh.nt_load, sh.nt_store,
-                       sh.min_blocks>,
+                       sh.min_blocks, sh.loads_first>,
         blocks, sh.block, stream, io, head, nvec, n);
   }
   int64_t blocks = (n + kScalarBlock - 1) / kScalarBlock;

@@ -96,3 +96,80 @@ def test_error_helpers_match_the_format_ulps():
     st = bench._err_stats(got, ref, 23, -126)
     assert st["max_abs"] == 2.0 ** -22
     assert st["max_ulp"] == 2.0
+
+
+def test_interleaved_alternates_blocks_and_takes_the_median_ratio():
+    """bench.interleaved times its two launch sequences in alternating
+    blocks (ten untimed launches, then the timed ones) and returns per-block
+    ms per launch and the median of time(b) / time(a)."""
+    calls, clock = [], [0.0]
+
+    class FakeEvent:
+        def __init__(self, enable_timing=False):
+            self.t = None
+
+        def record(self):
+            self.t = clock[0]
+
+        def elapsed_time(self, end):
+            return end.t - self.t
+
+    class Cuda:
+        Event = FakeEvent
+
+        @staticmethod
+        def synchronize():
+            pass
+
+    class Torch:
+        cuda = Cuda
+
+    cost = {"a": [1.0, 1.0, 2.0], "b": [1.25, 1.5, 2.0]}
+    rnd = {"a": 0, "b": 0}
+
+    def launcher(name):
+        def fn():
+            calls.append(name)
+            clock[0] += cost[name][rnd[name] // 14]
+            rnd[name] += 1
+        return fn
+
+    ta_ms, tb_ms, ratio = bench.interleaved(launcher("a"), launcher("b"), 3, 4,
+                                            Torch)
+    assert calls == (["a"] * 14 + ["b"] * 14) * 3
+    assert ta_ms == [1.0, 1.0, 2.0] and tb_ms == [1.25, 1.5, 2.0]
+    assert ratio == 1.25   # ratios 1.0, 1.25, 1.5
+
+
+def test_valu_model_reads_both_summaries(tmp_path, monkeypatch):
+    """bench.valu_cycles_per_elem combines the instruction counts of the two
+    SQ summaries with the per-class cycle costs: FP32 arithmetic 2 (4 in the
+    upper bound), FP64 arithmetic, conversions and INT64 4, FP32
+    transcendentals 8, the remaining instructions 3 (2 to 4); summaries of
+    other kernel sources give None."""
+    sha = bench.source_hash()
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    (prof / bench.SQ_SUMMARY).write_text(
+        f"source_sha: {sha}\n"
+        "k_SQ_INSTS_VALU: 1 per_elem 40.00\n"
+        "k_SQ_INSTS_VALU_FMA_F64: 1 per_elem 6.00\n"
+        "k_SQ_INSTS_VALU_CVT: 1 per_elem 4.00\n")
+    classes = {"FMA_F32": 10, "ADD_F32": 2, "MUL_F32": 4, "TRANS_F32": 1,
+               "ADD_F64": 1, "MUL_F64": 3, "INT64": 0}
+    (prof / bench.SQ_CLASS_SUMMARY).write_text(
+        f"source_sha: {sha}\n" + "".join(
+            f"k_SQ_INSTS_VALU_{c}: 1 per_elem {v:.2f}\n" for c, v in classes.items()))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "source_hash", lambda: sha)
+    # f32 16, trans 1, 4-cycle 6 + 1 + 3 + 4 + 0 = 14, rest 40 - 31 = 9
+    mid, lo, hi = bench.valu_cycles_per_elem("k")
+    assert (mid, lo, hi) == ((56 + 8 + 32 + 27) / 64, (56 + 8 + 32 + 18) / 64,
+                             (56 + 8 + 64 + 36) / 64)
+    r = bench.valu_roofline("k", 1e12)
+    assert r["bound"] == "alu" and r["valu_per_elem"] == 40.0
+    assert r["frac"] == round(1e12 * mid / bench.SIMD_CYCLES_PER_S, 3)
+    assert r["frac_range"][0] < r["frac"] < r["frac_range"][1]
+    assert bench.valu_cycles_per_elem("other") is None
+    monkeypatch.setattr(bench, "source_hash", lambda: "0" * 16)
+    assert bench.valu_cycles_per_elem("k") is None
