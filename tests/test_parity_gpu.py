@@ -470,6 +470,40 @@ def test_max_size_beyond_2_31_elements(dev):
     del x, y
 
 
+@pytest.mark.parametrize("kind", ["f32", "bf16", "f64"])
+def test_single_output_load_policy_threshold(dev, kind):
+    """A single input of at most 256 MiB is read with plain loads, a larger
+    one with the shape's nontemporal loads: on both sides of that size,
+    ta_sin, ta_cos and ta_tan give the bits of the sin, cos and tan outputs
+    of ta_sincos on the same input (the same arithmetic), and the Taylor
+    sine is the same below and above the size for a shared prefix."""
+    tdt = {"f32": torch.float32, "bf16": torch.bfloat16, "f64": torch.float64}[kind]
+    iv = {"f32": torch.int32, "bf16": torch.int16, "f64": torch.int64}[kind]
+    esz = torch.tensor([], dtype=tdt).element_size()
+    limit = (256 << 20) // esz
+    gen = torch.Generator(device=dev).manual_seed(977)
+    big = (torch.rand(limit + 37, device=dev, generator=gen, dtype=torch.float64)
+           * 2e3 - 1e3).to(tdt)
+    tay = {}
+    for n in (limit - 5, limit, limit + 37):
+        say(f"load policy {kind} n={n}")
+        x = big[:n]
+        ys, yc, yt = (torch.empty_like(x) for _ in range(3))
+        ta.ta_sincos(x, ys, yc, yt)
+        for fn, ref in ((ta.ta_sin, ys), (ta.ta_cos, yc), (ta.ta_tan, yt)):
+            y = torch.empty_like(x)
+            fn(x, y)
+            torch.cuda.synchronize()
+            assert torch.equal(y.view(iv), ref.view(iv)), (kind, n, fn.__name__)
+        yt5 = torch.empty_like(x)
+        ta.ta_taylor_sin(x, yt5, 5)
+        tay[n] = yt5[: limit - 5]
+        del ys, yc, yt
+    assert torch.equal(tay[limit - 5].view(iv), tay[limit + 37].view(iv))
+    assert torch.equal(tay[limit].view(iv), tay[limit + 37].view(iv))
+    del big, tay
+
+
 # ---------------------------------------------------------------------------
 # Taylor baseline
 # ---------------------------------------------------------------------------
