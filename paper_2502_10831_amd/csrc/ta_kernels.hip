@@ -533,8 +533,12 @@ struct IoPtrs {
 //     branch), the loads issued before the table fill (below): 819 Gelem/s
 //     against 789 for 256 threads with the fill first; 64 threads 763, four
 //     accesses 766, 72 VGPRs (seven waves) 804-808;
-//     one FP64 output, the tan guard or the paper-literal arithmetic:
-//     four accesses;
+//     one FP64 output, and one FP32 output with the tan guard or the
+//     paper-literal arithmetic (more than 64 VGPRs): 128 threads, two
+//     accesses, loads before the fill, no occupancy bound (FP64 sin 400
+//     Gelem/s against 374 for 256 threads with four accesses, FP64 tan 414
+//     against 385, FP32 guarded tan 788 against 752; one access 356-361 for
+//     FP64 sin);
 //   one FP32/FP64 output, light functors (Taylor, the built-ins; no table):
 //     one access, 128 threads (2 % above 256), nontemporal loads (sinf 860
 //     Gelem/s against 827 with plain loads);
@@ -563,7 +567,7 @@ struct Shape {
 };
 constexpr Shape kShapeMulti{256, 1, false, true};
 constexpr Shape kShapeSingle{128, 2, true, true, 8, true};
-constexpr Shape kShapeSingleWide{256, 4, true, true};
+constexpr Shape kShapeSingleWide{128, 2, true, true, 1, true};
 constexpr Shape kShapeMulti64{128, 1, false, true};
 constexpr Shape kShapeLight{128, 1, true, true};
 constexpr Shape kShapeTwoIn{128, 1, true, true};
@@ -603,8 +607,8 @@ constexpr Shape shape_for() {
                                          : kShapeMulti;
   // the functors that evaluate the method use the LDS table
   if (!Op::Table::kUsed) return kShapeLight;
-  // FP64 storage and the paper-literal FP64 arithmetic need more than 64
-  // VGPRs: four accesses per thread, no occupancy bound
+  // FP64 storage, and in FP32 the tan guard and the paper-literal FP64
+  // arithmetic, need more than 64 VGPRs: no occupancy bound
   if (sizeof(typename ST::raw) == 8 || wide_single<Op>::value ||
       std::is_same<typename Op::Table, PaperTables>::value)
     return kShapeSingleWide;
