@@ -993,13 +993,16 @@ __global__ __launch_bounds__(kScalarBlock) void map_scalar_kernel(IoPtrs io,
     scalar_element<ST, Op>(io, i, tb);
 }
 
-// One input stream of at most 256 MiB (the Infinity Cache's size) is read
-// with plain loads whatever the shape says: a launch after the one that wrote
-// or read the array then hits in the cache, which nontemporal loads would
-// pass by.  Single-output kernels on MI355X, arrays re-read launch after
-// launch: plain loads +7-34 % up to 256 MiB of input (FP32 sin at 2^23: 773
+// Inputs of at most 256 MiB in all (the Infinity Cache's size) are read with
+// plain loads whatever the shape says: a launch after the one that wrote or
+// read the arrays then hits in the cache, which nontemporal loads would pass
+// by.  On MI355X, arrays re-read launch after launch: single-output kernels
+// +7-34 % with plain loads up to 256 MiB of input (FP32 sin at 2^23: 773
 // against 651 Gelem/s; FP64 sin at 2^22: 400 against 297), nontemporal loads
-// +2-4 % from 512 MiB; below 32 MiB in and out either is the same.
+// +2-4 % from 512 MiB; the two- and three-input backward kernels the same
+// (sin backward +5-25 % up to 256 MiB read, -5 % from 512 MiB; the sincos
+// backward +18 % at 192 MiB, -3.5 % at 384 MiB); below 32 MiB in and out
+// either is the same.
 constexpr int64_t kCacheResidentBytes = int64_t(256) << 20;
 
 template <class ST, class Op>
@@ -1028,8 +1031,8 @@ hipError_t launch_map(const void *const *in, void *const *out, int64_t n,
     int64_t blocks = (nvec + per_block - 1) / per_block;
     if (blocks < 1) blocks = 1;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-    if constexpr (sh.nt_load && Op::NIN == 1) {
-      if (n <= kCacheResidentBytes / int64_t(sizeof(raw)))
+    if constexpr (sh.nt_load) {
+      if (n <= kCacheResidentBytes / int64_t(Op::NIN * sizeof(raw)))
         return launch(
             map_vec_kernel<ST, Op, sh.block, sh.unroll, false, sh.nt_store,
                            sh.min_blocks, sh.loads_first>,

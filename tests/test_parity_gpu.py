@@ -472,11 +472,12 @@ def test_max_size_beyond_2_31_elements(dev):
 
 @pytest.mark.parametrize("kind", ["f32", "bf16", "f64"])
 def test_single_output_load_policy_threshold(dev, kind):
-    """A single input of at most 256 MiB is read with plain loads, a larger
-    one with the shape's nontemporal loads: on both sides of that size,
+    """Inputs of at most 256 MiB in all are read with plain loads, larger
+    ones with the shape's nontemporal loads: on both sides of that size,
     ta_sin, ta_cos and ta_tan give the bits of the sin, cos and tan outputs
     of ta_sincos on the same input (the same arithmetic), and the Taylor
-    sine is the same below and above the size for a shared prefix."""
+    sine and the two- and three-input backward give the same bits below and
+    above the size for a shared prefix."""
     tdt = {"f32": torch.float32, "bf16": torch.bfloat16, "f64": torch.float64}[kind]
     iv = {"f32": torch.int32, "bf16": torch.int16, "f64": torch.int64}[kind]
     esz = torch.tensor([], dtype=tdt).element_size()
@@ -501,7 +502,23 @@ def test_single_output_load_policy_threshold(dev, kind):
         del ys, yc, yt
     assert torch.equal(tay[limit - 5].view(iv), tay[limit + 37].view(iv))
     assert torch.equal(tay[limit].view(iv), tay[limit + 37].view(iv))
-    del big, tay
+    del tay
+    # two and three inputs: the size counts all of them; the backward of a
+    # prefix gives the same bits below and above it
+    g1 = (torch.rand(limit + 37, device=dev, generator=gen,
+                     dtype=torch.float64) * 2 - 1).to(tdt)
+    g2 = g1.flip(0)
+    for nin, fn, args in ((2, ta.ta_sin_bwd, (g1,)), (3, ta.ta_sincos_bwd, (g1, g2))):
+        lim = limit // nin
+        outs = {}
+        for n in (lim - 5, lim + 37):
+            say(f"load policy {kind} {nin} inputs n={n}")
+            gx = torch.empty(n, device=dev, dtype=tdt)
+            fn(big[:n], *(a[:n] for a in args), gx)
+            outs[n] = gx
+        torch.cuda.synchronize()
+        assert torch.equal(outs[lim - 5].view(iv), outs[lim + 37][: lim - 5].view(iv)), nin
+    del big, g1, g2
 
 
 # ---------------------------------------------------------------------------
