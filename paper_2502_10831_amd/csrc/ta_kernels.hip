@@ -526,7 +526,8 @@ struct IoPtrs {
 // MI355X (2^27-2^29 elements):
 //   one input, several outputs: one 16-byte access per stream per thread,
 //     plain loads and device-scope nontemporal stores; 256 threads for FP32
-//     (7 % above 128), 128 for FP64 (3 % above 256);
+//     (7 % above 128), 128 for FP64 (3 % above 256 in one sweep, 12 % below
+//     it in another: where the arrays lie in memory decides);
 //   one FP32 output, the method (LDS table): 128 threads, two accesses per
 //     thread, nontemporal loads and stores, at most 64 VGPRs (eight waves per
 //     SIMD; the registers spilled are those of the rare large-argument
@@ -557,12 +558,13 @@ struct IoPtrs {
 // for one input and one output (FP32 sin +2.5-3.8 %, BF16 sin +1.7-2.2 %,
 // FP16 sin +0.6 %); the several-output kernels fill first (issuing their
 // loads earlier measured sin+cos+tan -4.2 %, sin+cos -3.6 %, BF16
-// sin+cos+tan -0.3 %, FP64 sin+cos+tan -0.7 %), and the backward and FP64
-// single-output kernels showed no difference either way.
+// sin+cos+tan -0.3 %, FP64 sin+cos+tan -0.7 %), and the backward kernels
+// showed no difference either way (FP64 single output: +3.6 % at 128
+// threads with two accesses, none at 256 threads with four).
 struct Shape {
   int block, unroll;
   bool nt_load, nt_store;
-  int min_blocks = 1;  // __launch_bounds__ minimum waves per SIMD
+  int min_waves = 1;  // __launch_bounds__ minimum waves per SIMD
   bool loads_first = false;
 };
 constexpr Shape kShapeMulti{256, 1, false, true};
@@ -1035,12 +1037,12 @@ hipError_t launch_map(const void *const *in, void *const *out, int64_t n,
       if (n <= kCacheResidentBytes / int64_t(Op::NIN * sizeof(raw)))
         return launch(
             map_vec_kernel<ST, Op, sh.block, sh.unroll, false, sh.nt_store,
-                           sh.min_blocks, sh.loads_first>,
+                           sh.min_waves, sh.loads_first>,
             blocks, sh.block, stream, io, head, nvec, n);
     }
     return launch(
         map_vec_kernel<ST, Op, sh.block, sh.unroll, sh.nt_load, sh.nt_store,
-                       sh.min_blocks, sh.loads_first>,
+                       sh.min_waves, sh.loads_first>,
         blocks, sh.block, stream, io, head, nvec, n);
   }
   int64_t blocks = (n + kScalarBlock - 1) / kScalarBlock;
