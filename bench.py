@@ -492,6 +492,15 @@ def comparators(x, x_host, n, args, torch, ta, np):
                             "accuracy_stats_vs_libm": stats(outs),
                             "sample": "2^20 random elements of the workload",
                             "jump_band_elements_in_sample": int(band.sum())}
+    # the method again on these output arrays, so that it and the built-ins
+    # share one placement in memory
+    def fm():
+        ta.ta_sincos(x, ys, yc, yt)
+    log("timing ta_sincos on the comparators' arrays")
+    per, total, _ = time_launches(fm, args.steps, args.warmup, torch, WARM_S)
+    ms = total / args.steps
+    res["ta_sincos_tan"]["gelem_s_same_arrays_as_builtins"] = round(
+        n / (ms * 1e-3) / 1e9, 2)
     for kind, label in ((0, "builtin_sinf_cosf_tanf"),
                         (1, "builtin___sinf___cosf___tanf")):
         def f(kind=kind):
