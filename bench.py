@@ -1109,8 +1109,9 @@ def summarize(a):
         directory, out, cmd = a[1], a[2], " ".join(a[3:])
         # per-dispatch records: the bench also launches these kernels at other
         # sizes, so keep the dispatches of the headline shapes (grid = one
-        # thread per 16-byte FP32 vector of the workload)
-        grids = {"sincos_tan_f32": (1 << 28) // 4,
+        # thread per 16-byte vector of the workload, and per four of them
+        # for the fused FP32 kernel)
+        grids = {"sincos_tan_f32": (1 << 28) // 16,
                  "sin_fwdbwd_f32": 128 * 8192 * 512 // 4,
                  "sincos_tan_f64": (1 << 27) // 2}
         algo = {"sincos_tan_f32": 16 * (1 << 28),

@@ -524,10 +524,18 @@ struct IoPtrs {
 
 // Launch shape of the vector body, per kernel category, chosen by timing on
 // MI355X (2^27-2^29 elements):
-//   one input, several outputs: one 16-byte access per stream per thread,
-//     plain loads and device-scope nontemporal stores; 256 threads for FP32
-//     (7 % above 128), 128 for FP64 (3 % above 256 in one sweep, 12 % below
-//     it in another: where the arrays lie in memory decides);
+//   one input, several outputs: plain loads and device-scope nontemporal
+//     stores; FP32 sin, cos and tan of the method: 64 threads, four
+//     accesses per thread, every output computed before the stores, then
+//     each output array's four stores together (232 VGPRs, two waves per
+//     SIMD; over 16 array placements in two processes it beat 256 threads
+//     with one access on every one, mean 6.41 against 6.11 TB/s, worst 6.18
+//     against 5.75; the same shape storing per access 5.67, 128 threads
+//     grouped 6.30; for two outputs, 16-bit storage and FP64 grouping was
+//     slower); other FP32 multi-output kernels one access per stream per
+//     thread and 256 threads (7 % above 128); FP64 128 threads (3 % above
+//     256 in one sweep, 12 % below it in another: where the arrays lie in
+//     memory decides);
 //   one FP32 output, the method (LDS table): 128 threads, two accesses per
 //     thread, nontemporal loads and stores, at most 64 VGPRs (eight waves per
 //     SIMD; the registers spilled are those of the rare large-argument
@@ -566,8 +574,10 @@ struct Shape {
   bool nt_load, nt_store;
   int min_waves = 1;  // __launch_bounds__ minimum waves per SIMD
   bool loads_first = false;
+  bool grouped = false;  // all outputs computed, then each array's stores
 };
 constexpr Shape kShapeMulti{256, 1, false, true};
+constexpr Shape kShapeMulti3{64, 4, false, true, 1, false, true};
 constexpr Shape kShapeSingle{128, 2, true, true, 8, true};
 constexpr Shape kShapeSingleWide{128, 2, true, true, 1, true};
 constexpr Shape kShapeMulti64{128, 1, false, true};
@@ -604,6 +614,12 @@ constexpr Shape shape_for() {
   }
   if (Op::NIN >= 2)
     return Op::NOUT == 1 ? kShapeTwoIn1 : kShapeTwoIn;
+  // the method's sin, cos and tan of FP32 storage with the FP64 forms (not
+  // the carried FP32 evaluation, whose grouped form measured slower, nor
+  // the paper-literal arithmetic)
+  if (Op::NOUT == 3 && sizeof(typename ST::raw) == 4 &&
+      std::is_same<typename Op::Table, TablesFwd>::value)
+    return kShapeMulti3;
   if (Op::NOUT >= 2)
     return sizeof(typename ST::raw) == 8 ? kShapeMulti64
                                          : kShapeMulti;
@@ -672,10 +688,12 @@ __device__ inline void scalar_element(const IoPtrs &io, int64_t i,
 // Vector body: elements [head, head + nvec*VEC) in 16-byte accesses, UNROLL
 // accesses per stream per thread, all loads issued before any compute (LF:
 // also before the table fill and its barrier); NTS: the stores go through
-// SpanStore.  The workgroup with blockIdx 0 also does the scalar head
-// [0, head) and tail [head + nvec*VEC, n).
+// SpanStore; GROUP: every output is computed before any store, then each
+// output array's UNROLL stores are issued together.  The workgroup with
+// blockIdx 0 also does the scalar head [0, head) and tail
+// [head + nvec*VEC, n).
 template <class ST, class Op, int BLOCK, int UNROLL, bool NTL, bool NTS,
-          int MINB, bool LF>
+          int MINB, bool LF, bool GROUP>
 __global__ __launch_bounds__(BLOCK, MINB) void map_vec_kernel(IoPtrs io, int64_t head,
                                                         int64_t nvec, int64_t n) {
   using raw = typename ST::raw;
@@ -701,16 +719,29 @@ __global__ __launch_bounds__(BLOCK, MINB) void map_vec_kernel(IoPtrs io, int64_t
     if (v < nvec) {
 #pragma unroll
       for (int k = 0; k < Op::NIN; ++k) in_raw[u][k] = vload<NTL, typename ST::vec>(in_base[k], v);
+    } else if constexpr (GROUP) {
+#pragma unroll
+      for (int k = 0; k < Op::NIN; ++k) in_raw[u][k] = typename ST::vec{};
     }
   }
   if constexpr (Op::Table::kUsed && LF) {
     Op::Table::init(tb);
     __syncthreads();
   }
+  using vec = typename ST::vec;
+  constexpr int kVB = int(sizeof(vec));
+  constexpr int kSpan = UNROLL * BLOCK * kVB;
+  const int64_t span0 = int64_t(blockIdx.x) * (UNROLL * BLOCK);
+  static_assert(!GROUP || NTS, "grouped stores go through SpanStore");
+  vec out_raw[GROUP ? UNROLL : 1][Op::NOUT];
 #pragma unroll
   for (int u = 0; u < UNROLL; ++u) {
     const int64_t v = v0 + int64_t(u) * BLOCK;
-    if (v < nvec) {
+    // GROUP: every vector is computed, past the end on zeros, so that the
+    // UNROLL evaluations are straight-line code the compiler interleaves
+    // (under one branch each they ran one after another: 5.82 against
+    // 6.46 TB/s)
+    if (GROUP || v < nvec) {
       using val = typename ST::val;
       val arg[Op::NIN][VEC], res[Op::NOUT][VEC];
 #pragma unroll
@@ -726,16 +757,25 @@ __global__ __launch_bounds__(BLOCK, MINB) void map_vec_kernel(IoPtrs io, int64_t
       }
 #pragma unroll
       for (int k = 0; k < Op::NOUT; ++k) {
-        if constexpr (NTS) {
-          constexpr int kSpan = UNROLL * BLOCK * int(sizeof(typename ST::vec));
-          const int64_t span0 = int64_t(blockIdx.x) * (UNROLL * BLOCK);
-          const SpanStore ss(out_base[k] + span0 * int64_t(sizeof(typename ST::vec)),
-                             kSpan);
-          ss.put(uint32_t(v - span0) * uint32_t(sizeof(typename ST::vec)),
-                 ST::pack(res[k]));
+        if constexpr (GROUP) {
+          out_raw[u][k] = ST::pack(res[k]);
+        } else if constexpr (NTS) {
+          const SpanStore ss(out_base[k] + span0 * kVB, kSpan);
+          ss.put(uint32_t(v - span0) * uint32_t(kVB), ST::pack(res[k]));
         } else {
           vstore<false>(out_base[k], v, ST::pack(res[k]));
         }
+      }
+    }
+  }
+  if constexpr (GROUP) {
+#pragma unroll
+    for (int k = 0; k < Op::NOUT; ++k) {
+      const SpanStore ss(out_base[k] + span0 * kVB, kSpan);
+#pragma unroll
+      for (int u = 0; u < UNROLL; ++u) {
+        const int64_t v = v0 + int64_t(u) * BLOCK;
+        if (v < nvec) ss.put(uint32_t(v - span0) * uint32_t(kVB), out_raw[u][k]);
       }
     }
   }
@@ -1007,6 +1047,29 @@ __global__ __launch_bounds__(kScalarBlock) void map_scalar_kernel(IoPtrs io,
 // either is the same.
 constexpr int64_t kCacheResidentBytes = int64_t(256) << 20;
 
+// The vector body in shape SH over [head, head + nvec*VEC) (plus the scalar
+// head and tail), with the load policy by size above.
+template <class ST, class Op, const Shape &SH>
+hipError_t launch_vec(const IoPtrs &io, int64_t head, int64_t nvec, int64_t n,
+                      hipStream_t stream) {
+  using raw = typename ST::raw;
+  const int64_t per_block = int64_t(SH.unroll) * SH.block;
+  int64_t blocks = (nvec + per_block - 1) / per_block;
+  if (blocks < 1) blocks = 1;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  if constexpr (SH.nt_load) {
+    if (n <= kCacheResidentBytes / int64_t(Op::NIN * sizeof(raw)))
+      return launch(
+          map_vec_kernel<ST, Op, SH.block, SH.unroll, false, SH.nt_store,
+                         SH.min_waves, SH.loads_first, SH.grouped>,
+          blocks, SH.block, stream, io, head, nvec, n);
+  }
+  return launch(
+      map_vec_kernel<ST, Op, SH.block, SH.unroll, SH.nt_load, SH.nt_store,
+                     SH.min_waves, SH.loads_first, SH.grouped>,
+      blocks, SH.block, stream, io, head, nvec, n);
+}
+
 template <class ST, class Op>
 hipError_t launch_map(const void *const *in, void *const *out, int64_t n,
                       hipStream_t stream, uint32_t flags) {
@@ -1028,22 +1091,15 @@ hipError_t launch_map(const void *const *in, void *const *out, int64_t n,
     int64_t head = mis ? int64_t((16u - mis) / sizeof(raw)) : 0;
     if (head > n) head = n;
     const int64_t nvec = (n - head) / VEC;
-    constexpr Shape sh = shape_for<ST, Op>();
-    const int64_t per_block = int64_t(sh.unroll) * sh.block;
-    int64_t blocks = (nvec + per_block - 1) / per_block;
-    if (blocks < 1) blocks = 1;
-    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-    if constexpr (sh.nt_load) {
+    static constexpr Shape sh = shape_for<ST, Op>();
+    // the grouped shape is for streams from HBM; inputs that fit the
+    // Infinity Cache take the one-access shape (sin+cos+tan at 2^22-2^26
+    // FP32: 0.2-11 % faster that way, 1-1.5 % slower from 2^27)
+    if constexpr (sh.grouped) {
       if (n <= kCacheResidentBytes / int64_t(Op::NIN * sizeof(raw)))
-        return launch(
-            map_vec_kernel<ST, Op, sh.block, sh.unroll, false, sh.nt_store,
-                           sh.min_waves, sh.loads_first>,
-            blocks, sh.block, stream, io, head, nvec, n);
+        return launch_vec<ST, Op, kShapeMulti>(io, head, nvec, n, stream);
     }
-    return launch(
-        map_vec_kernel<ST, Op, sh.block, sh.unroll, sh.nt_load, sh.nt_store,
-                       sh.min_waves, sh.loads_first>,
-        blocks, sh.block, stream, io, head, nvec, n);
+    return launch_vec<ST, Op, sh>(io, head, nvec, n, stream);
   }
   int64_t blocks = (n + kScalarBlock - 1) / kScalarBlock;
   if (blocks > 65536) blocks = 65536;

@@ -48,8 +48,9 @@ def _write_trace(path, rows):
 
 def test_trace_summary_on_a_synthetic_trace(tmp_path):
     name = ("void ta::map_vec_kernel<ta::F32, ta::FwdOp<7, false, false, "
-            "false, false>, 256, 1, false, true, 1>(ta::IoPtrs, long, long, long)")
-    grid = (1 << 28) // 4
+            "false, false>, 64, 4, false, true, 1, false, true>(ta::IoPtrs, "
+            "long, long, long)")
+    grid = (1 << 28) // 16   # 64-thread groups, four 16-byte vectors a thread
     rows, t = [], 0
     warm, steps = 1733, bench.HEADLINE_STEPS   # a time-based warm-up count
     copy = "void ta::map_vec_kernel<ta::F32, ta::CopyOp<1, 3>, 64, 1, false, true, 1>"
