@@ -1108,12 +1108,16 @@ def summarize(a):
     if mode == "trace":
         directory, out, cmd = a[1], a[2], " ".join(a[3:])
         # per-dispatch records: the bench also launches these kernels at other
-        # sizes, so keep the dispatches of the headline shapes (grid = one
-        # thread per 16-byte vector of the workload, and per four of them
-        # for the fused FP32 kernel)
+        # sizes, so keep the dispatches of the headline shapes by grid and
+        # workgroup size (grid = one thread per 16-byte vector of the
+        # workload, and per four of them in the fused FP32 kernel's 64-thread
+        # groups; its 256-thread launches over 2^26 elements have the same
+        # grid)
         grids = {"sincos_tan_f32": (1 << 28) // 16,
                  "sin_fwdbwd_f32": 128 * 8192 * 512 // 4,
                  "sincos_tan_f64": (1 << 27) // 2}
+        groups = {"sincos_tan_f32": 64, "sin_fwdbwd_f32": 128,
+                  "sincos_tan_f64": 128}
         algo = {"sincos_tan_f32": 16 * (1 << 28),
                 "sin_fwdbwd_f32": 16 * 128 * 8192 * 512,
                 "sincos_tan_f64": 32 * (1 << 27)}
@@ -1122,7 +1126,8 @@ def summarize(a):
         for r in _csv_rows(directory, "kernel_trace.csv"):
             key = _which(r.get("Kernel_Name", ""))
             t0, t1 = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
-            hit = key in grids and int(r["Grid_Size_X"]) == grids[key]
+            hit = (key in grids and int(r["Grid_Size_X"]) == grids[key]
+                   and int(r["Workgroup_Size_X"]) == groups[key])
             if hit:
                 recs.setdefault(key, []).append((t0, t1 - t0))
             order.append((t0, hit and key == "sincos_tan_f32", t1 - t0))
@@ -1133,7 +1138,8 @@ def summarize(a):
             rs.sort()  # dispatch order
             d = sorted(x for _, x in rs)
             avg_ns = sum(d) / len(d)
-            lines.append(f"{key}: grid {grids[key]} calls {len(d)} "
+            lines.append(f"{key}: grid {grids[key]} workgroup "
+                         f"{groups[key]} calls {len(d)} "
                          f"average_ns {avg_ns:.0f} median_ns {d[len(d) // 2]} "
                          f"min_ns {d[0]} max_ns {d[-1]}")
             lines.append(f"{key}_algorithmic_GBs: {algo[key] / avg_ns:.1f}")

@@ -41,6 +41,7 @@ def _write_trace(path, rows):
     os.makedirs(os.path.dirname(path), exist_ok=True)
     with open(path, "w", newline="") as f:
         w = csv.DictWriter(f, fieldnames=["Kernel_Name", "Grid_Size_X",
+                                          "Workgroup_Size_X",
                                           "Start_Timestamp", "End_Timestamp"])
         w.writeheader()
         w.writerows(rows)
@@ -57,20 +58,31 @@ def test_trace_summary_on_a_synthetic_trace(tmp_path):
     for i in range(warm + steps + 10):
         if i == warm + steps:   # the copy ceiling runs next, then more calls
             rows.append({"Kernel_Name": copy, "Grid_Size_X": grid,
+                         "Workgroup_Size_X": 64,
                          "Start_Timestamp": t, "End_Timestamp": t + 900_000})
             t += 901_000
         dur = 800_000 if i < warm or i >= warm + steps else 700_000
         rows.append({"Kernel_Name": name, "Grid_Size_X": grid,
+                     "Workgroup_Size_X": 64,
                      "Start_Timestamp": t, "End_Timestamp": t + dur})
         t += dur + 1000
-    # a dispatch of the same kernel at another size is not counted
+    # dispatches of the same kernel at another size are not counted: another
+    # grid, or the same grid in 256-thread groups (2^26 elements, one vector
+    # a thread)
     rows.append({"Kernel_Name": name, "Grid_Size_X": 1024,
+                 "Workgroup_Size_X": 64,
                  "Start_Timestamp": t, "End_Timestamp": t + 5})
+    small = name.replace("64, 4, false, true, 1, false, true",
+                         "256, 1, false, true, 1, false, false")
+    rows.append({"Kernel_Name": small, "Grid_Size_X": grid,
+                 "Workgroup_Size_X": 256,
+                 "Start_Timestamp": t + 10, "End_Timestamp": t + 150_000})
     _write_trace(str(tmp_path / "trace" / "run_kernel_trace.csv"), rows)
     out = str(tmp_path / "summary.txt")
     bench.summarize(["trace", str(tmp_path / "trace"), out, "cmd"])
     text = open(out).read()
-    assert f"sincos_tan_f32: grid {grid} calls {warm + steps + 10}" in text
+    assert (f"sincos_tan_f32: grid {grid} workgroup 64 "
+            f"calls {warm + steps + 10}") in text
     assert (f"sincos_tan_f32_headline_timed: the last {steps} of the first "
             f"{warm + steps} back-to-back dispatches, average_ns 700000") in text
     assert f"source_sha: {bench.source_hash()}" in text
