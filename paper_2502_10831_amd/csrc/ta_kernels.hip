@@ -527,7 +527,7 @@ struct IoPtrs {
 //   one input, several outputs: plain loads and device-scope nontemporal
 //     stores; FP32 sin, cos and tan of the method: 64 threads, four
 //     accesses per thread, every output computed before the stores, then
-//     each output array's four stores together (232 VGPRs, two waves per
+//     each output array's four stores together (240 VGPRs, two waves per
 //     SIMD; over 16 array placements in two processes it beat 256 threads
 //     with one access on every one, mean 6.41 against 6.11 TB/s, worst 6.18
 //     against 5.75; the same shape storing per access 5.67, 128 threads
@@ -615,8 +615,9 @@ constexpr Shape shape_for() {
   if (Op::NIN >= 2)
     return Op::NOUT == 1 ? kShapeTwoIn1 : kShapeTwoIn;
   // the method's sin, cos and tan of FP32 storage with the FP64 forms (not
-  // the carried FP32 evaluation, whose grouped form measured slower, nor
-  // the paper-literal arithmetic)
+  // the carried FP32 evaluation, whose grouped form measured no faster,
+  // 6.16 against 6.15 TB/s over eight placements, nor the paper-literal
+  // arithmetic)
   if (Op::NOUT == 3 && sizeof(typename ST::raw) == 4 &&
       std::is_same<typename Op::Table, TablesFwd>::value)
     return kShapeMulti3;
