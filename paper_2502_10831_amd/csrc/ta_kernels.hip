@@ -532,7 +532,7 @@ struct IoPtrs {
 //     with one access on every one, mean 6.41 against 6.11 TB/s, worst 6.18
 //     against 5.75; the same shape storing per access 5.67, 128 threads
 //     grouped 6.30; for two outputs, 16-bit storage and FP64 grouping was
-//     slower); other FP32 multi-output kernels one access per stream per
+//     slower), the loads issued before the table fill (below); other FP32 multi-output kernels one access per stream per
 //     thread and 256 threads (7 % above 128); FP64 128 threads (3 % above
 //     256 in one sweep, 12 % below it in another: where the arrays lie in
 //     memory decides);
@@ -564,9 +564,11 @@ struct IoPtrs {
 // loads_first: the kernel issues its loads, then fills the LDS table and
 // waits at the barrier, so the fill overlaps the loads' latency.  That pays
 // for one input and one output (FP32 sin +2.5-3.8 %, BF16 sin +1.7-2.2 %,
-// FP16 sin +0.6 %); the several-output kernels fill first (issuing their
-// loads earlier measured sin+cos+tan -4.2 %, sin+cos -3.6 %, BF16
-// sin+cos+tan -0.3 %, FP64 sin+cos+tan -0.7 %), and the backward kernels
+// FP16 sin +0.6 %) and for the grouped FP32 sin+cos+tan (+1.2 %, ahead on
+// 14 of 16 placements); the other several-output kernels fill first
+// (issuing their loads earlier measured sin+cos+tan in 256-thread groups
+// -4.2 %, sin+cos -3.6 %, BF16 sin+cos+tan -0.3 %, FP64 sin+cos+tan
+// -0.7 %), and the backward kernels
 // showed no difference either way (FP64 single output: +3.6 % at 128
 // threads with two accesses, none at 256 threads with four).
 struct Shape {
@@ -577,7 +579,7 @@ struct Shape {
   bool grouped = false;  // all outputs computed, then each array's stores
 };
 constexpr Shape kShapeMulti{256, 1, false, true};
-constexpr Shape kShapeMulti3{64, 4, false, true, 1, false, true};
+constexpr Shape kShapeMulti3{64, 4, false, true, 1, true, true};
 constexpr Shape kShapeSingle{128, 2, true, true, 8, true};
 constexpr Shape kShapeSingleWide{128, 2, true, true, 1, true};
 constexpr Shape kShapeMulti64{128, 1, false, true};

@@ -131,4 +131,7 @@ def decode_16(u: np.ndarray, kind: str) -> np.ndarray:
     u = np.asarray(u, np.uint16)
     if kind == "f16":
         return u.view(np.float16).astype(np.float64)
-    return (u.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    # signalling-NaN patterns raise numpy's "invalid" flag when widened (they
+    # come out as quiet NaNs); every other pattern widens exactly
+    with np.errstate(invalid="ignore"):
+        return (u.astype(np.uint32) << 16).view(np.float32).astype(np.float64)

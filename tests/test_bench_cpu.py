@@ -49,7 +49,7 @@ def _write_trace(path, rows):
 
 def test_trace_summary_on_a_synthetic_trace(tmp_path):
     name = ("void ta::map_vec_kernel<ta::F32, ta::FwdOp<7, false, false, "
-            "false, false>, 64, 4, false, true, 1, false, true>(ta::IoPtrs, "
+            "false, false>, 64, 4, false, true, 1, true, true>(ta::IoPtrs, "
             "long, long, long)")
     grid = (1 << 28) // 16   # 64-thread groups, four 16-byte vectors a thread
     rows, t = [], 0
@@ -72,7 +72,7 @@ def test_trace_summary_on_a_synthetic_trace(tmp_path):
     rows.append({"Kernel_Name": name, "Grid_Size_X": 1024,
                  "Workgroup_Size_X": 64,
                  "Start_Timestamp": t, "End_Timestamp": t + 5})
-    small = name.replace("64, 4, false, true, 1, false, true",
+    small = name.replace("64, 4, false, true, 1, true, true",
                          "256, 1, false, true, 1, false, false")
     rows.append({"Kernel_Name": small, "Grid_Size_X": grid,
                  "Workgroup_Size_X": 256,
