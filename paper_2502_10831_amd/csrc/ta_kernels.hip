@@ -53,7 +53,7 @@ struct F32 {
 
 // 16-bit formats round pairs: a <2 x float> -> <2 x half|bfloat>
 // conversion is one v_cvt_pk_{f16,bf16}_f32.  Accesses of 8 elements (16
-// bytes, 46-52 VGPRs with the FP32 evaluation).
+// bytes, 44-50 VGPRs for the method with the FP32 evaluation).
 template <class Derived>
 struct Half16 {
   using raw = uint16_t;
@@ -814,14 +814,20 @@ hipError_t launch(void (*kernel)(KArgs...), int64_t blocks, int threads,
 // (every plane then starts 16-byte aligned at element `head`), U of them per
 // thread, block-strided, so that per frequency a workgroup writes U * 2 KiB
 // contiguous to each plane and issues the U stores of one plane together;
-// otherwise one element per lane.  128-thread groups with nontemporal stores.
-// At 2^26 FP32 inputs and 8 frequencies, U = 4 moves 6.47 TB/s against 6.02
-// for U = 1 (0.94 of the same-run write-only fill); launch bounds asking for
-// two or four waves per SIMD made the compiler spill and fall to ~0.95 TB/s.
-constexpr int kEncodeBlock = 128;
+// otherwise one element per lane.  Nontemporal device-scope stores.  At 2^26
+// FP32 inputs and 8 frequencies, U = 4 moves 6.47 TB/s against 6.02 for
+// U = 1 (0.94 of the same-run write-only fill); launch bounds asking for two
+// or four waves per SIMD made the compiler spill and fall to ~0.95 TB/s.
+// FP32 runs one-wave groups (ahead of 128 threads on 12 of 12 array
+// placements in two processes, mean +0.9 %; issuing the loads before the
+// table fill added nothing), BF16 and FP64 128-thread groups.
 template <class ST>
 constexpr int encode_unroll() {
   return sizeof(typename ST::raw) == 4 ? 4 : 1;
+}
+template <class ST>
+constexpr int encode_block() {
+  return sizeof(typename ST::raw) == 4 ? 64 : 128;
 }
 __device__ inline float pow2(int j, float) {
   return __uint_as_float(uint32_t(127 + j) << 23);
@@ -829,8 +835,8 @@ __device__ inline float pow2(int j, float) {
 __device__ inline double pow2(int j, double) {
   return __longlong_as_double(int64_t(1023 + j) << 52);
 }
-template <class ST, bool VEC_PATH, int UNROLL>
-__global__ __launch_bounds__(kEncodeBlock) void encode_kernel(
+template <class ST, bool VEC_PATH, int UNROLL, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void encode_kernel(
     const char *x, char *y, int64_t n, int nfreq, int64_t head, int64_t nvec) {
   using raw = typename ST::raw;
   using val = typename ST::val;
@@ -841,12 +847,12 @@ __global__ __launch_bounds__(kEncodeBlock) void encode_kernel(
   Core::Table::init(tb);
   __syncthreads();
   const int64_t plane = n * int64_t(sizeof(raw));
-  const int64_t v0 = int64_t(blockIdx.x) * (U * kEncodeBlock) + threadIdx.x;
+  const int64_t v0 = int64_t(blockIdx.x) * (U * BLOCK) + threadIdx.x;
   const char *xb = x + head * int64_t(sizeof(raw));
   val xf[U][VEC];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    const int64_t v = v0 + int64_t(u) * kEncodeBlock;
+    const int64_t v = v0 + int64_t(u) * BLOCK;
 #pragma unroll
     for (int e = 0; e < VEC; ++e) xf[u][e] = val(0);
     if (v < nvec) {
@@ -876,17 +882,17 @@ __global__ __launch_bounds__(kEncodeBlock) void encode_kernel(
       if constexpr (VEC_PATH) {
         // this group's span of each plane, one SpanStore each
         constexpr int kVB = int(sizeof(typename ST::vec));
-        const int64_t span0 = int64_t(blockIdx.x) * (U * kEncodeBlock);
-        const SpanStore ss(ps + span0 * kVB, U * kEncodeBlock * kVB);
-        const SpanStore sc(pc + span0 * kVB, U * kEncodeBlock * kVB);
+        const int64_t span0 = int64_t(blockIdx.x) * (U * BLOCK);
+        const SpanStore ss(ps + span0 * kVB, U * BLOCK * kVB);
+        const SpanStore sc(pc + span0 * kVB, U * BLOCK * kVB);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          const int64_t v = v0 + int64_t(u) * kEncodeBlock;
+          const int64_t v = v0 + int64_t(u) * BLOCK;
           if (v < nvec) ss.put(uint32_t(v - span0) * kVB, ST::pack(sv[u]));
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          const int64_t v = v0 + int64_t(u) * kEncodeBlock;
+          const int64_t v = v0 + int64_t(u) * BLOCK;
           if (v < nvec) sc.put(uint32_t(v - span0) * kVB, ST::pack(cv[u]));
         }
       } else {
@@ -900,7 +906,7 @@ __global__ __launch_bounds__(kEncodeBlock) void encode_kernel(
   if (VEC_PATH && blockIdx.x == 0) {  // scalar head and tail
     const int64_t tail0 = head + nvec * VEC;
     const int64_t extra = head + (n - tail0);
-    for (int64_t e = threadIdx.x; e < extra; e += kEncodeBlock) {
+    for (int64_t e = threadIdx.x; e < extra; e += BLOCK) {
       const int64_t i = e < head ? e : tail0 + (e - head);
       const val xi = ST::load(reinterpret_cast<const raw *>(x)[i]);
       for (int j = 0; j < nfreq; ++j) {
@@ -928,16 +934,18 @@ hipError_t launch_encode(const void *x, void *y, int64_t n, int nfreq,
     int64_t head = mis ? int64_t((16u - mis) / sizeof(raw)) : 0;
     if (head > n) head = n;
     const int64_t nvec = (n - head) / VEC;
-    const int64_t per = int64_t(encode_unroll<ST>()) * kEncodeBlock;
+    constexpr int kBlock = encode_block<ST>();
+    const int64_t per = int64_t(encode_unroll<ST>()) * kBlock;
     int64_t blocks = (nvec + per - 1) / per;
     if (blocks < 1) blocks = 1;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-    return launch(encode_kernel<ST, true, encode_unroll<ST>()>, blocks,
-                  kEncodeBlock, stream, xc, yc, n, nfreq, head, nvec);
+    return launch(encode_kernel<ST, true, encode_unroll<ST>(), kBlock>,
+                  blocks, kBlock, stream, xc, yc, n, nfreq, head, nvec);
   } else {
-    const int64_t blocks = (n + kEncodeBlock - 1) / kEncodeBlock;
+    constexpr int kBlock = 128;
+    const int64_t blocks = (n + kBlock - 1) / kBlock;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-    return launch(encode_kernel<ST, false, 1>, blocks, kEncodeBlock, stream,
+    return launch(encode_kernel<ST, false, 1, kBlock>, blocks, kBlock, stream,
                   xc, yc, n, nfreq, int64_t(0), n);
   }
 }
