@@ -523,6 +523,43 @@ def test_single_output_load_policy_threshold(dev, kind):
     del big, g1, g2
 
 
+@pytest.mark.parametrize("off", [1, 3])
+def test_grouped_kernel_shared_misalignment(dev, off):
+    """FP32 sin+cos+tan on more than 256 MiB of input runs the grouped
+    four-vector kernel.  With the input and the three outputs all `off`
+    elements past a 16-byte boundary (a scalar head of 4 - off elements,
+    the 16-byte body ending in a partial workgroup, a scalar tail), every
+    element equals that of the same call on aligned buffers, and the ends
+    plus 2^20 elements spread over the array are within the FP32 rule of
+    the oracle."""
+    n = (256 << 20) // 4 + 1037
+    gen = torch.Generator(device=dev).manual_seed(979)
+    x = (torch.rand(n, device=dev, generator=gen, dtype=torch.float64)
+         * 2e3 - 1e3).to(torch.float32)
+    say(f"grouped kernel shared misalignment off={off} n={n}")
+
+    def at_offset(t=None):
+        buf = torch.empty(n + off, device=dev)
+        assert buf.data_ptr() % 16 == 0
+        if t is not None:
+            buf[off:].copy_(t)
+        return buf[off:]
+
+    ref = [torch.empty_like(x) for _ in range(3)]
+    ta.ta_sincos(x, *ref)
+    outs = [at_offset() for _ in range(3)]
+    ta.ta_sincos(at_offset(x), *outs)
+    torch.cuda.synchronize()
+    for a, b in zip(ref, outs):
+        assert torch.equal(a.view(torch.int32), b.view(torch.int32)), off
+    idx = np.unique(np.concatenate([
+        np.arange(4096), np.arange(n - 4096, n),
+        np.linspace(0, n - 1, 1 << 20).astype(np.int64)]))
+    got = {k: host(t)[idx] for k, t in zip(("f3_sin", "f3_cos", "f3_tan"), outs)}
+    check_all_f32(host(x)[idx], got, f"grouped off={off}")
+    del x, ref, outs
+
+
 # ---------------------------------------------------------------------------
 # Taylor baseline
 # ---------------------------------------------------------------------------
