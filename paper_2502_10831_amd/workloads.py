@@ -109,7 +109,9 @@ def round_to_16(x: np.ndarray, kind: str) -> np.ndarray:
     raw uint16 patterns."""
     x = np.asarray(x, np.float64)
     if kind == "f16":
-        return x.astype(np.float16).view(np.uint16)
+        # beyond the FP16 range the nearest-even result is +-Inf
+        with np.errstate(over="ignore"):
+            return x.astype(np.float16).view(np.uint16)
     if kind != "bf16":
         raise ValueError(kind)
     # BF16 = top half of FP32: round FP64 -> BF16 directly (no double

@@ -58,9 +58,9 @@ def _compare(name, got, ref, tol_ulp, scale=None):
     r = np.asarray(ref, np.longdouble)
     both_nan = np.isnan(g) & np.isnan(r.astype(np.float64))
     same_inf = np.isinf(g) & (g == r.astype(np.float64))
-    err = np.abs(g.astype(np.longdouble) - r)
     s = r if scale is None else scale
-    with np.errstate(invalid="ignore", divide="ignore"):
+    with np.errstate(invalid="ignore", divide="ignore"):   # inf - inf, NaN
+        err = np.abs(g.astype(np.longdouble) - r)
         e_ulp = (err / _ulp(s)).astype(np.float64)
     ok = both_nan | same_inf | (e_ulp <= tol_ulp)
     e_ulp = np.where(both_nan | same_inf, 0.0, e_ulp)

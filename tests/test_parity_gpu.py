@@ -944,7 +944,8 @@ def test_encode_16bit_exhaustive(dev, kind):
     y = ta.encode(xd, nfreq)
     got = host(y.view(torch.int16)).view(np.uint16)
     for j in range(nfreq):
-        xj = x64 * 2.0 ** j
+        with np.errstate(invalid="ignore"):   # the NaN patterns
+            xj = x64 * 2.0 ** j
         fin = np.abs(xj) < 3.0e38   # 2^j x stays finite in FP32
         ref = oracle.forward(xj[fin])
         for k, name in ((2 * j, "sin"), (2 * j + 1, "cos")):
