@@ -531,11 +531,15 @@ struct IoPtrs {
 //     SIMD; over 16 array placements in two processes it beat 256 threads
 //     with one access on every one, mean 6.41 against 6.11 TB/s, worst 6.18
 //     against 5.75; the same shape storing per access 5.67, 128 threads
-//     grouped 6.30; for two outputs, 16-bit storage and FP64 grouping was
-//     slower), the loads issued before the table fill (below); other FP32 multi-output kernels one access per stream per
-//     thread and 256 threads (7 % above 128); FP64 128 threads (3 % above
-//     256 in one sweep, 12 % below it in another: where the arrays lie in
-//     memory decides);
+//     grouped 6.30), the loads issued before the table fill (below); FP32
+//     sin and cos of the method the same with two accesses per thread
+//     (ahead of 256 threads with one access on 13 of 16 placements, mean
+//     6.52 against 6.38 TB/s; four accesses 6.26, 128 threads 6.42); for
+//     16-bit storage and FP64 grouping was no faster; the other FP32
+//     multi-output kernels one access per stream per thread and 256
+//     threads (7 % above 128); FP64 128 threads (3 % above 256 in one
+//     sweep, 12 % below it in another: where the arrays lie in memory
+//     decides);
 //   one FP32 output, the method (LDS table): 128 threads, two accesses per
 //     thread, nontemporal loads and stores, at most 64 VGPRs (eight waves per
 //     SIMD; the registers spilled are those of the rare large-argument
@@ -580,6 +584,7 @@ struct Shape {
 };
 constexpr Shape kShapeMulti{256, 1, false, true};
 constexpr Shape kShapeMulti3{64, 4, false, true, 1, true, true};
+constexpr Shape kShapeMulti2{64, 2, false, true, 1, true, true};
 constexpr Shape kShapeSingle{128, 2, true, true, 8, true};
 constexpr Shape kShapeSingleWide{128, 2, true, true, 1, true};
 constexpr Shape kShapeMulti64{128, 1, false, true};
@@ -616,13 +621,16 @@ constexpr Shape shape_for() {
   }
   if (Op::NIN >= 2)
     return Op::NOUT == 1 ? kShapeTwoIn1 : kShapeTwoIn;
-  // the method's sin, cos and tan of FP32 storage with the FP64 forms (not
-  // the carried FP32 evaluation, whose grouped form measured no faster,
-  // 6.16 against 6.15 TB/s over eight placements, nor the paper-literal
-  // arithmetic)
+  // the method's sin, cos (and tan) of FP32 storage with the FP64 forms
+  // (not the carried FP32 evaluation, whose grouped form measured no
+  // faster, 6.16 against 6.15 TB/s over eight placements, nor the
+  // paper-literal arithmetic)
   if (Op::NOUT == 3 && sizeof(typename ST::raw) == 4 &&
       std::is_same<typename Op::Table, TablesFwd>::value)
     return kShapeMulti3;
+  if (Op::NOUT == 2 && sizeof(typename ST::raw) == 4 &&
+      std::is_same<typename Op::Table, TablesFwd>::value)
+    return kShapeMulti2;
   if (Op::NOUT >= 2)
     return sizeof(typename ST::raw) == 8 ? kShapeMulti64
                                          : kShapeMulti;

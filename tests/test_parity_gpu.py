@@ -475,9 +475,11 @@ def test_max_size_beyond_2_31_elements(dev):
 @pytest.mark.parametrize("kind", ["f32", "bf16", "f64"])
 def test_single_output_load_policy_threshold(dev, kind):
     """Inputs of at most 256 MiB in all are read with plain loads, larger
-    ones with the shape's nontemporal loads: on both sides of that size,
-    ta_sin, ta_cos and ta_tan give the bits of the sin, cos and tan outputs
-    of ta_sincos on the same input (the same arithmetic), and the Taylor
+    ones with the shape's nontemporal loads (and FP32 sin+cos with or
+    without tan in the grouped multi-vector kernels): on both sides of that
+    size, ta_sin, ta_cos and ta_tan, and ta_sincos without tan, give the
+    bits of the sin, cos and tan outputs of ta_sincos on the same input
+    (the same arithmetic), and the Taylor
     sine and the two- and three-input backward give the same bits below and
     above the size for a shared prefix."""
     tdt = {"f32": torch.float32, "bf16": torch.bfloat16, "f64": torch.float64}[kind]
@@ -498,6 +500,12 @@ def test_single_output_load_policy_threshold(dev, kind):
             fn(x, y)
             torch.cuda.synchronize()
             assert torch.equal(y.view(iv), ref.view(iv)), (kind, n, fn.__name__)
+        ys2, yc2 = torch.empty_like(x), torch.empty_like(x)
+        ta.ta_sincos(x, ys2, yc2, None)
+        torch.cuda.synchronize()
+        assert torch.equal(ys2.view(iv), ys.view(iv)), (kind, n, "sin of two")
+        assert torch.equal(yc2.view(iv), yc.view(iv)), (kind, n, "cos of two")
+        del ys2, yc2
         yt5 = torch.empty_like(x)
         ta.ta_taylor_sin(x, yt5, 5)
         tay[n] = yt5[: limit - 5]
@@ -526,10 +534,11 @@ def test_single_output_load_policy_threshold(dev, kind):
 @pytest.mark.parametrize("off", [1, 3])
 def test_grouped_kernel_shared_misalignment(dev, off):
     """FP32 sin+cos+tan on more than 256 MiB of input runs the grouped
-    four-vector kernel.  With the input and the three outputs all `off`
-    elements past a 16-byte boundary (a scalar head of 4 - off elements,
-    the 16-byte body ending in a partial workgroup, a scalar tail), every
-    element equals that of the same call on aligned buffers, and the ends
+    four-vector kernel, sin+cos the grouped two-vector one.  With the input
+    and the outputs all `off` elements past a 16-byte boundary (a scalar
+    head of 4 - off elements, the 16-byte body ending in a partial
+    workgroup, a scalar tail), every element equals that of the same call
+    on aligned buffers (and sin+cos those of sin+cos+tan), and the ends
     plus 2^20 elements spread over the array are within the FP32 rule of
     the oracle."""
     n = (256 << 20) // 4 + 1037
@@ -552,6 +561,12 @@ def test_grouped_kernel_shared_misalignment(dev, off):
     torch.cuda.synchronize()
     for a, b in zip(ref, outs):
         assert torch.equal(a.view(torch.int32), b.view(torch.int32)), off
+    two = [at_offset() for _ in range(2)]
+    ta.ta_sincos(at_offset(x), two[0], two[1], None)
+    torch.cuda.synchronize()
+    for a, b in zip(ref, two):
+        assert torch.equal(a.view(torch.int32), b.view(torch.int32)), (off, 2)
+    del two
     idx = np.unique(np.concatenate([
         np.arange(4096), np.arange(n - 4096, n),
         np.linspace(0, n - 1, 1 << 20).astype(np.int64)]))
