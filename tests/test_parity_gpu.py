@@ -505,6 +505,14 @@ def test_single_output_load_policy_threshold(dev, kind):
         torch.cuda.synchronize()
         assert torch.equal(ys2.view(iv), ys.view(iv)), (kind, n, "sin of two")
         assert torch.equal(yc2.view(iv), yc.view(iv)), (kind, n, "cos of two")
+        if kind == "f32":   # the tan guard through the fused kernels too
+            yg = torch.empty_like(x)
+            ta.ta_tan_ex(x, yg, ta.TA_FLAG_TAN_GUARD)
+            ta.ta_sincos_ex(x, ys2, yc2, yt, ta.TA_FLAG_TAN_GUARD)
+            torch.cuda.synchronize()
+            assert torch.equal(yt.view(iv), yg.view(iv)), (kind, n, "guard")
+            assert torch.equal(ys2.view(iv), ys.view(iv)), (kind, n, "guard sin")
+            del yg
         del ys2, yc2
         yt5 = torch.empty_like(x)
         ta.ta_taylor_sin(x, yt5, 5)
