@@ -3,7 +3,8 @@
 // Every entry point is an elementwise map: NIN input streams, NOUT output
 // streams, one functor per element.  The streaming skeleton issues 16-byte
 // global loads and stores (4 FP32, 8 FP16/BF16 or 2 FP64 elements per
-// access), with a launch shape per kernel category (see shape_for) and
+// access; 8-byte accesses of 4 FP16/BF16 elements for one input and several
+// outputs), with a launch shape per kernel category (see shape_for) and
 // 64-bit indexing.  The
 // per-piece coefficients live in LDS (one copy of 176-360 bytes per
 // workgroup, by kernel family), never in HBM.
@@ -52,14 +53,15 @@ struct F32 {
 };
 
 // 16-bit formats round pairs: a <2 x float> -> <2 x half|bfloat>
-// conversion is one v_cvt_pk_{f16,bf16}_f32.  Accesses of 8 elements (16
-// bytes, 44-50 VGPRs for the method with the FP32 evaluation).
-template <class Derived>
+// conversion is one v_cvt_pk_{f16,bf16}_f32.  Accesses of NV elements: 8
+// (16 bytes, 44-50 VGPRs for the method with the FP32 evaluation) or 4 (8
+// bytes; the one-input, several-output kernels, below).
+template <class Derived, int NV>
 struct Half16 {
   using raw = uint16_t;
   using val = float;
-  static constexpr int kVec = 8;
-  using vec = u32x4;
+  static constexpr int kVec = NV;
+  using vec = typename std::conditional<NV == 8, u32x4, u32x2>::type;
   static __device__ void unpack(const vec &w, val *v) {
     raw h[kVec];
     __builtin_memcpy(h, &w, sizeof(vec));
@@ -74,7 +76,9 @@ struct Half16 {
     return w;
   }
 };
-struct F16 : Half16<F16> {
+template <int NV>
+struct F16T : Half16<F16T<NV>, NV> {
+  using raw = uint16_t;
   static __device__ float load(raw v) {
     return float(__builtin_bit_cast(_Float16, v));
   }
@@ -86,7 +90,9 @@ struct F16 : Half16<F16> {
     return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, f16x2));
   }
 };
-struct BF16 : Half16<BF16> {
+template <int NV>
+struct BF16T : Half16<BF16T<NV>, NV> {
+  using raw = uint16_t;
   static __device__ float load(raw v) { return __uint_as_float(uint32_t(v) << 16); }
   static __device__ raw store(float f) {
     return __builtin_bit_cast(raw, __bf16(f));
@@ -96,6 +102,16 @@ struct BF16 : Half16<BF16> {
     return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
   }
 };
+
+using F16 = F16T<8>;
+using BF16 = BF16T<8>;
+// One input and several outputs of 16-bit storage take 8-byte accesses, two
+// per thread in 256-thread groups: BF16 sin+cos+tan over 16 array placements
+// in two processes 6.43 against 6.17 TB/s for one 16-byte access per thread
+// (ahead on 15), sin+cos 6.42 against 6.36; one 8-byte access 6.26 and
+// 5.89, two in 128-thread groups 6.22 and 6.39.
+using F16x4 = F16T<4>;
+using BF16x4 = BF16T<4>;
 
 struct F64 {
   using raw = uint64_t;
@@ -561,10 +577,11 @@ struct IoPtrs {
 //   16-bit storage: one input and one output, 128 threads and two accesses
 //     per thread with nontemporal loads, loads before the fill (BF16 sin
 //     1663 Gelem/s against 1634 with the fill first and 1495 with four
-//     8-byte accesses); every other category 256 threads and one access, with
-//     plain loads for one input and several outputs (BF16 sin+cos+tan 6.28
-//     against 6.19 TB/s with nontemporal loads) and nontemporal loads for two
-//     or more inputs.
+//     8-byte accesses); one input and several outputs 8-byte accesses (the
+//     F16x4/BF16x4 storage), two per thread in 256-thread groups, plain
+//     loads (BF16 sin+cos+tan 6.28 against 6.19 TB/s with nontemporal loads
+//     at one 16-byte access); two or more inputs one 16-byte access per
+//     thread in 256-thread groups, nontemporal loads.
 // loads_first: the kernel issues its loads, then fills the LDS table and
 // waits at the barrier, so the fill overlaps the loads' latency.  That pays
 // for one input and one output (FP32 sin +2.5-3.8 %, BF16 sin +1.7-2.2 %,
@@ -592,7 +609,7 @@ constexpr Shape kShapeLight{128, 1, true, true};
 constexpr Shape kShapeTwoIn{128, 1, true, true};
 constexpr Shape kShapeTwoIn1{128, 2, true, true};
 constexpr Shape kShapeHalfSingle{128, 2, true, true, 1, true};
-constexpr Shape kShapeHalfMulti{256, 1, false, true};
+constexpr Shape kShapeHalfMulti{256, 2, false, true};
 constexpr Shape kShapeHalf{256, 1, true, true};
 // The copy comparators (the HBM ceiling a kernel is compared with): one
 // wave per workgroup, the fastest plain copy of 1 -> 3 and 2 -> 2 FP32
@@ -679,6 +696,9 @@ struct SpanStore {
       : r(__builtin_amdgcn_make_buffer_rsrc(span, 0, bytes, kBufferWord3)) {}
   __device__ void put(uint32_t byte_off, u32x4 x) const {
     __builtin_amdgcn_raw_buffer_store_b128(x, r, byte_off, 0, kStoreNtDevice);
+  }
+  __device__ void put(uint32_t byte_off, u32x2 x) const {
+    __builtin_amdgcn_raw_buffer_store_b64(x, r, byte_off, 0, kStoreNtDevice);
   }
 };
 
@@ -1131,8 +1151,16 @@ hipError_t launch_dtype(ta_dtype dt, const void *const *in, void *const *out,
                         int64_t n, hipStream_t s, uint32_t flags) {
   switch (dt) {
     case TA_F32: return launch_map<F32, Op>(in, out, n, s, flags);
-    case TA_F16: return launch_map<F16, typename Op::LowH>(in, out, n, s, flags);
-    case TA_BF16: return launch_map<BF16, typename Op::Low>(in, out, n, s, flags);
+    case TA_F16:
+      if constexpr (Op::LowH::NIN == 1 && Op::LowH::NOUT >= 2)
+        return launch_map<F16x4, typename Op::LowH>(in, out, n, s, flags);
+      else
+        return launch_map<F16, typename Op::LowH>(in, out, n, s, flags);
+    case TA_BF16:
+      if constexpr (Op::Low::NIN == 1 && Op::Low::NOUT >= 2)
+        return launch_map<BF16x4, typename Op::Low>(in, out, n, s, flags);
+      else
+        return launch_map<BF16, typename Op::Low>(in, out, n, s, flags);
     case TA_F64: return launch_map<F64, Op>(in, out, n, s, flags);
     default: break;
   }
