@@ -1065,8 +1065,8 @@ KERNELS = {
     "copy_1to1_f32": ("F32", "CopyOp<1, 1>"),
     "sin_fwdbwd_f32": ("F32", "BwdOp<1, true, false, false>"),
     "sin_f32": ("F32", "FwdOp<1, false, false, false, false>"),
-    "sincos_tan_bf16": ("BF16", "FwdOp<7, false, true, false, false>"),
-    "sin_bf16": ("BF16", "FwdOp<1, false, true, false, false>"),
+    "sincos_tan_bf16": ("BF16T<4>", "FwdOp<7, false, true, false, false>"),
+    "sin_bf16": ("BF16T<8>", "FwdOp<1, false, true, false, false>"),
     "sincos_tan_f64": ("F64", "FwdOp<7, false, false, false, false>"),
     "encode_f32": ("F32", "encode_kernel<"),
 }

@@ -186,3 +186,22 @@ def test_valu_model_reads_both_summaries(tmp_path, monkeypatch):
     assert bench.valu_cycles_per_elem("other") is None
     monkeypatch.setattr(bench, "source_hash", lambda: "0" * 16)
     assert bench.valu_cycles_per_elem("k") is None
+
+
+def test_every_profiled_kernel_has_rows_in_the_committed_summaries():
+    """Each kernel `bench.py --profile` dispatches is named in every committed
+    counter summary: a kernel whose name no longer matches its pattern in
+    bench.KERNELS (a renamed storage type, say) would drop out of the
+    traffic, instruction and stall summaries without an error."""
+    prof = os.path.join(bench.ROOT, "profiles")
+    for fname, suffix in (("ta_sincos_tan_f32_2p28_pmc.txt",
+                           "_traffic_over_algorithmic:"),
+                          (bench.SQ_SUMMARY, "_SQ_INSTS_VALU:"),
+                          (bench.SQ_CLASS_SUMMARY, "_SQ_INSTS_VALU_FMA_F32:"),
+                          ("ta_kernels_f32_bf16_f64_stall_counters.txt",
+                           "_SQ_WAVE_CYCLES:")):
+        text = open(os.path.join(prof, fname)).read()
+        for key in bench.KERNELS:
+            if key == "copy_1to1_f32" and "traffic" in suffix:
+                continue   # the calibration copy itself
+            assert f"\n{key}{suffix}" in text, (fname, key)
