@@ -109,7 +109,11 @@ using BF16 = BF16T<8>;
 // per thread in 256-thread groups: BF16 sin+cos+tan over 16 array placements
 // in two processes 6.43 against 6.17 TB/s for one 16-byte access per thread
 // (ahead on 15), sin+cos 6.42 against 6.36; one 8-byte access 6.26 and
-// 5.89, two in 128-thread groups 6.22 and 6.39.
+// 5.89, two in 128-thread groups 6.22 and 6.39.  The fused forward and
+// backward (two inputs, two outputs) takes one 8-byte access per thread in
+// its 256-thread shape above 256 MiB of input: BF16 at 2^29 elements 6.48
+// against 6.29 TB/s over 12 placements (ahead on 12); two accesses in
+// 128-thread groups 6.55.
 using F16x4 = F16T<4>;
 using BF16x4 = BF16T<4>;
 
@@ -547,13 +551,14 @@ struct IoPtrs {
 //     SIMD; over 16 array placements in two processes it beat 256 threads
 //     with one access on every one, mean 6.41 against 6.11 TB/s, worst 6.18
 //     against 5.75; the same shape storing per access 5.67, 128 threads
-//     grouped 6.30), the loads issued before the table fill (below); FP32
-//     sin and cos of the method the same with two accesses per thread
-//     (ahead of 256 threads with one access on 13 of 16 placements, mean
-//     6.52 against 6.38 TB/s; four accesses 6.26, 128 threads 6.42); for
-//     16-bit storage and FP64 grouping was no faster; the other FP32
-//     multi-output kernels one access per stream per thread and 256
-//     threads (7 % above 128); FP64 128 threads (3 % above 256 in one
+//     grouped 6.30), the loads issued before the table fill (below); for
+//     FP32 sin and cos grouping measured +2 % over 16 placements of one
+//     probe but equal (6.36 against 6.37 TB/s, ahead on 4 of 8) after the
+//     launches the benchmark times before it, and below the one-access
+//     shape in the benchmark itself (513-517 against 520-535 Gelem/s), so
+//     it keeps one access; for 16-bit storage and FP64 grouping was no
+//     faster; the other FP32 multi-output kernels one access per stream per
+//     thread and 256 threads (7 % above 128); FP64 128 threads (3 % above 256 in one
 //     sweep, 12 % below it in another: where the arrays lie in memory
 //     decides);
 //   one FP32 output, the method (LDS table): 128 threads, two accesses per
@@ -580,8 +585,9 @@ struct IoPtrs {
 //     8-byte accesses); one input and several outputs 8-byte accesses (the
 //     F16x4/BF16x4 storage), two per thread in 256-thread groups, plain
 //     loads (BF16 sin+cos+tan 6.28 against 6.19 TB/s with nontemporal loads
-//     at one 16-byte access); two or more inputs one 16-byte access per
-//     thread in 256-thread groups, nontemporal loads.
+//     at one 16-byte access); two or more inputs one access per thread in
+//     256-thread groups (8 bytes for two outputs above 256 MiB of input, 16
+//     otherwise), nontemporal loads.
 // loads_first: the kernel issues its loads, then fills the LDS table and
 // waits at the barrier, so the fill overlaps the loads' latency.  That pays
 // for one input and one output (FP32 sin +2.5-3.8 %, BF16 sin +1.7-2.2 %,
@@ -601,7 +607,6 @@ struct Shape {
 };
 constexpr Shape kShapeMulti{256, 1, false, true};
 constexpr Shape kShapeMulti3{64, 4, false, true, 1, true, true};
-constexpr Shape kShapeMulti2{64, 2, false, true, 1, true, true};
 constexpr Shape kShapeSingle{128, 2, true, true, 8, true};
 constexpr Shape kShapeSingleWide{128, 2, true, true, 1, true};
 constexpr Shape kShapeMulti64{128, 1, false, true};
@@ -638,16 +643,13 @@ constexpr Shape shape_for() {
   }
   if (Op::NIN >= 2)
     return Op::NOUT == 1 ? kShapeTwoIn1 : kShapeTwoIn;
-  // the method's sin, cos (and tan) of FP32 storage with the FP64 forms
-  // (not the carried FP32 evaluation, whose grouped form measured no
-  // faster, 6.16 against 6.15 TB/s over eight placements, nor the
-  // paper-literal arithmetic)
+  // the method's sin, cos and tan of FP32 storage with the FP64 forms (not
+  // the carried FP32 evaluation, whose grouped form measured no faster,
+  // 6.16 against 6.15 TB/s over eight placements, nor the paper-literal
+  // arithmetic)
   if (Op::NOUT == 3 && sizeof(typename ST::raw) == 4 &&
       std::is_same<typename Op::Table, TablesFwd>::value)
     return kShapeMulti3;
-  if (Op::NOUT == 2 && sizeof(typename ST::raw) == 4 &&
-      std::is_same<typename Op::Table, TablesFwd>::value)
-    return kShapeMulti2;
   if (Op::NOUT >= 2)
     return sizeof(typename ST::raw) == 8 ? kShapeMulti64
                                          : kShapeMulti;
@@ -1146,21 +1148,33 @@ hipError_t launch_map(const void *const *in, void *const *out, int64_t n,
                 n);
 }
 
+// 16-bit storage takes 8-byte accesses (F16x4/BF16x4) for one input and
+// several outputs, and for two inputs and two outputs (the fused forward and
+// backward) on inputs above 256 MiB; 16-byte ones otherwise.  (The fused
+// forward and backward over [64, 4096, 256] BF16, 256 MiB of input, ran at
+// 772 Gelem/s with 8-byte accesses against 833 with 16-byte ones in the
+// benchmark's sequence of launches.)
+template <class Op>
+bool eight_byte_16bit(int64_t n) {
+  if constexpr (Op::NIN == 1 && Op::NOUT >= 2) return true;
+  if constexpr (Op::NIN == 2 && Op::NOUT == 2)
+    return n > kCacheResidentBytes / int64_t(2 * sizeof(uint16_t));
+  return false;
+}
+
 template <class Op>
 hipError_t launch_dtype(ta_dtype dt, const void *const *in, void *const *out,
                         int64_t n, hipStream_t s, uint32_t flags) {
   switch (dt) {
     case TA_F32: return launch_map<F32, Op>(in, out, n, s, flags);
     case TA_F16:
-      if constexpr (Op::LowH::NIN == 1 && Op::LowH::NOUT >= 2)
+      if (eight_byte_16bit<typename Op::LowH>(n))
         return launch_map<F16x4, typename Op::LowH>(in, out, n, s, flags);
-      else
-        return launch_map<F16, typename Op::LowH>(in, out, n, s, flags);
+      return launch_map<F16, typename Op::LowH>(in, out, n, s, flags);
     case TA_BF16:
-      if constexpr (Op::Low::NIN == 1 && Op::Low::NOUT >= 2)
+      if (eight_byte_16bit<typename Op::Low>(n))
         return launch_map<BF16x4, typename Op::Low>(in, out, n, s, flags);
-      else
-        return launch_map<BF16, typename Op::Low>(in, out, n, s, flags);
+      return launch_map<BF16, typename Op::Low>(in, out, n, s, flags);
     case TA_F64: return launch_map<F64, Op>(in, out, n, s, flags);
     default: break;
   }

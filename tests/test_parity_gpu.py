@@ -475,13 +475,13 @@ def test_max_size_beyond_2_31_elements(dev):
 @pytest.mark.parametrize("kind", ["f32", "bf16", "f64"])
 def test_single_output_load_policy_threshold(dev, kind):
     """Inputs of at most 256 MiB in all are read with plain loads, larger
-    ones with the shape's nontemporal loads (and FP32 sin+cos with or
-    without tan in the grouped multi-vector kernels): on both sides of that
+    ones with the shape's nontemporal loads (and FP32 sin+cos+tan in the
+    grouped four-vector kernel): on both sides of that
     size, ta_sin, ta_cos and ta_tan, and ta_sincos without tan, give the
     bits of the sin, cos and tan outputs of ta_sincos on the same input
-    (the same arithmetic), and the Taylor
-    sine and the two- and three-input backward give the same bits below and
-    above the size for a shared prefix."""
+    (the same arithmetic), and the Taylor sine, the two- and three-input
+    backward and the fused forward and backward give the same bits below
+    and above the size for a shared prefix."""
     tdt = {"f32": torch.float32, "bf16": torch.bfloat16, "f64": torch.float64}[kind]
     iv = {"f32": torch.int32, "bf16": torch.int16, "f64": torch.int64}[kind]
     esz = torch.tensor([], dtype=tdt).element_size()
@@ -536,14 +536,27 @@ def test_single_output_load_policy_threshold(dev, kind):
             outs[n] = gx
         torch.cuda.synchronize()
         assert torch.equal(outs[lim - 5].view(iv), outs[lim + 37][: lim - 5].view(iv)), nin
-    del big, g1, g2
+    # the fused forward and backward (two inputs, two outputs; 16-bit
+    # storage changes its access width at the size): the same bits below
+    # and above it
+    lim = limit // 2
+    fb = {}
+    for n in (lim - 5, lim + 37):
+        say(f"load policy {kind} fused forward+backward n={n}")
+        y, gx = (torch.empty(n, device=dev, dtype=tdt) for _ in range(2))
+        ta.ta_sin_fwdbwd(big[:n], g1[:n], y, gx)
+        fb[n] = (y, gx)
+    torch.cuda.synchronize()
+    for a, b in zip(fb[lim - 5], fb[lim + 37]):
+        assert torch.equal(a.view(iv), b[: lim - 5].view(iv)), "fwdbwd"
+    del big, g1, g2, fb
 
 
 @pytest.mark.parametrize("off", [1, 3])
 def test_grouped_kernel_shared_misalignment(dev, off):
     """FP32 sin+cos+tan on more than 256 MiB of input runs the grouped
-    four-vector kernel, sin+cos the grouped two-vector one.  With the input
-    and the outputs all `off` elements past a 16-byte boundary (a scalar
+    four-vector kernel.  With the input and the outputs (of sin+cos+tan,
+    and of sin+cos) all `off` elements past a 16-byte boundary (a scalar
     head of 4 - off elements, the 16-byte body ending in a partial
     workgroup, a scalar tail), every element equals that of the same call
     on aligned buffers (and sin+cos those of sin+cos+tan), and the ends
